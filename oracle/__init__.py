@@ -1,0 +1,316 @@
+"""CPU oracle for the Mat2Stencil hot path -- TEST INFRASTRUCTURE ONLY.
+
+Thin numpy/ctypes front end over libm2s_oracle.so (plain single-threaded C,
+built from m2s_oracle.c with -O2 -ffp-contract=off).  Only tests/, the smoke
+check and the benchmark's CPU-baseline leg import this package; the HIP
+library and its Python binding never do, and the two share no code.
+
+Array conventions: scalar fields are numpy arrays of shape (nz, ny, nx)
+(x fastest); BLOCK7 fields are (nz, ny, nx, 5); VAR7 face arrays are
+kx (nz, ny, nx+1), ky (nz, ny+1, nx), kz (nz+1, ny, nx); BLOCK7 blocks are
+(7, 5, 5) in the order centre, -x, +x, -y, +y, -z, +z.  Functions never
+modify their inputs; "in-place" sweeps work on a copy that is returned.
+
+Each wrapped routine cites the part of the paper it follows in the C source.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "libm2s_oracle.so")
+_lib = None
+
+PC_NONE, PC_SYMGS, PC_MG, PC_MG_F32 = 0, 1, 2, 3
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_fp = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        from . import build as _b  # noqa: F401  (oracle/build.py)
+        _b.build()
+    lib = C.CDLL(_LIBPATH)
+    i, d, f = C.c_int, C.c_double, C.c_float
+    for sfx, P, R in (("_f64", _dp, d), ("_f32", _fp, f)):
+        g = lambda n: getattr(lib, "m2so_" + n + sfx)  # noqa: E731
+        g("spmv27").argtypes = [i, i, i, R, R, P, P]
+        g("symgs27_fwd").argtypes = [i, i, i, R, R, P, P]
+        g("symgs27_bwd").argtypes = [i, i, i, R, R, P, P]
+        g("spmv27_part").argtypes = [i, i, i, R, i, P, P]
+        g("spmv_var7").argtypes = [i, i, i, P, P, P, P, P]
+        g("spmv_var7_part").argtypes = [i, i, i, P, P, P, i, P, P]
+        g("symgs_var7_fwd").argtypes = [i, i, i, P, P, P, P, P]
+        g("symgs_var7_bwd").argtypes = [i, i, i, P, P, P, P, P]
+        g("var7_coarsen").argtypes = [i, i, i, P, P, P, P, P, P]
+        g("var7_face_grad").argtypes = [i, i, i, P, P, P, P, P]
+        g("spmv_block7").argtypes = [i, i, i, P, P, P]
+        g("ssor_block7_fwd").argtypes = [i, i, i, P, R, P, P]
+        g("ssor_block7_bwd").argtypes = [i, i, i, P, R, P, P]
+        g("ssor_block7_fwd").restype = i
+        g("ssor_block7_bwd").restype = i
+        g("restrict_inject").argtypes = [i, i, i, P, P, P]
+        g("prolong_inject").argtypes = [i, i, i, P, P]
+        g("mg_create").restype = C.c_void_p
+        g("mg_create").argtypes = [i, i, i, i, i, R, R, C.c_void_p,
+                                   C.c_void_p, C.c_void_p]
+        g("mg_destroy").argtypes = [C.c_void_p]
+        g("mg_vcycle").argtypes = [C.c_void_p, P, P]
+        g("mg_faces").restype = C.c_void_p
+        g("mg_faces").argtypes = [C.c_void_p, i, i]
+        g("lu5_factor").argtypes = [P, P, np.ctypeslib.ndpointer(
+            dtype=np.int32, flags="C_CONTIGUOUS")]
+        g("lu5_factor").restype = i
+    lib.m2so_pcg.restype = i
+    lib.m2so_pcg.argtypes = [i, i, i, i, d, d, C.c_void_p, C.c_void_p,
+                             C.c_void_p, i, i, _dp, _dp, i, d, i,
+                             C.POINTER(i), C.POINTER(d), C.POINTER(d),
+                             C.c_void_p]
+    _lib = lib
+    return lib
+
+
+def _sfx(dtype):
+    if dtype == np.float64:
+        return "_f64"
+    if dtype == np.float32:
+        return "_f32"
+    raise TypeError(f"oracle supports float64/float32, got {dtype}")
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _fn(name, dtype):
+    return getattr(_load(), "m2so_" + name + _sfx(np.dtype(dtype)))
+
+
+# ---------------------------------------------------------------- CONST27
+def spmv27(x, diag=26.0, off=-1.0, dtype=np.float64):
+    """y = A x for the constant 27-point operator (Dirichlet truncation)."""
+    x = _c(x, dtype)
+    nz, ny, nx = x.shape
+    y = np.empty_like(x)
+    _fn("spmv27", dtype)(nx, ny, nz, diag, off, x, y)
+    return y
+
+
+def spmv27_part(x, part, off=-1.0, dtype=np.float64):
+    """Strict lower (part=-1) or upper (part=+1) triangle of CONST27 times x."""
+    x = _c(x, dtype)
+    nz, ny, nx = x.shape
+    y = np.empty_like(x)
+    _fn("spmv27_part", dtype)(nx, ny, nz, off, int(part), x, y)
+    return y
+
+
+def symgs27(r, x, direction="sym", diag=26.0, off=-1.0, dtype=np.float64):
+    """Lexicographic Gauss-Seidel sweep(s) on CONST27.
+
+    direction: "fwd" (p ascending), "bwd" (p descending) or "sym" (fwd then
+    bwd, one symmetric Gauss-Seidel).  Returns the updated copy of x."""
+    r = _c(r, dtype)
+    x = np.array(x, dtype=dtype, copy=True, order="C")
+    nz, ny, nx = r.shape
+    if direction in ("fwd", "sym"):
+        _fn("symgs27_fwd", dtype)(nx, ny, nz, diag, off, r, x)
+    if direction in ("bwd", "sym"):
+        _fn("symgs27_bwd", dtype)(nx, ny, nz, diag, off, r, x)
+    if direction not in ("fwd", "bwd", "sym"):
+        raise ValueError(direction)
+    return x
+
+
+# ---------------------------------------------------------------- VAR7
+def spmv_var7(x, kx, ky, kz, dtype=np.float64):
+    x = _c(x, dtype)
+    nz, ny, nx = x.shape
+    y = np.empty_like(x)
+    _fn("spmv_var7", dtype)(nx, ny, nz, _c(kx, dtype), _c(ky, dtype),
+                            _c(kz, dtype), x, y)
+    return y
+
+
+def spmv_var7_part(x, kx, ky, kz, part, dtype=np.float64):
+    x = _c(x, dtype)
+    nz, ny, nx = x.shape
+    y = np.empty_like(x)
+    _fn("spmv_var7_part", dtype)(nx, ny, nz, _c(kx, dtype), _c(ky, dtype),
+                                 _c(kz, dtype), int(part), x, y)
+    return y
+
+
+def symgs_var7(r, x, kx, ky, kz, direction="sym", dtype=np.float64):
+    r = _c(r, dtype)
+    x = np.array(x, dtype=dtype, copy=True, order="C")
+    nz, ny, nx = r.shape
+    args = (nx, ny, nz, _c(kx, dtype), _c(ky, dtype), _c(kz, dtype), r, x)
+    if direction in ("fwd", "sym"):
+        _fn("symgs_var7_fwd", dtype)(*args)
+    if direction in ("bwd", "sym"):
+        _fn("symgs_var7_bwd", dtype)(*args)
+    if direction not in ("fwd", "bwd", "sym"):
+        raise ValueError(direction)
+    return x
+
+
+def var7_coarsen(kx, ky, kz, dtype=np.float64):
+    kx, ky, kz = _c(kx, dtype), _c(ky, dtype), _c(kz, dtype)
+    nz, ny, nx1 = kx.shape
+    nx = nx1 - 1
+    cx, cy, cz = nx // 2, ny // 2, nz // 2
+    kxc = np.empty((cz, cy, cx + 1), dtype)
+    kyc = np.empty((cz, cy + 1, cx), dtype)
+    kzc = np.empty((cz + 1, cy, cx), dtype)
+    _fn("var7_coarsen", dtype)(nx, ny, nz, kx, ky, kz, kxc, kyc, kzc)
+    return kxc, kyc, kzc
+
+
+def var7_face_grad(u, lam, dtype=np.float64):
+    """dL/dk_f = -(lam_p - lam_q)(u_p - u_q) for every face (zero ghosts)."""
+    u, lam = _c(u, dtype), _c(lam, dtype)
+    nz, ny, nx = u.shape
+    gx = np.empty((nz, ny, nx + 1), dtype)
+    gy = np.empty((nz, ny + 1, nx), dtype)
+    gz = np.empty((nz + 1, ny, nx), dtype)
+    _fn("var7_face_grad", dtype)(nx, ny, nz, u, lam, gx, gy, gz)
+    return gx, gy, gz
+
+
+# ---------------------------------------------------------------- BLOCK7
+def spmv_block7(x, blocks, dtype=np.float64):
+    x = _c(x, dtype)
+    nz, ny, nx, nv = x.shape
+    assert nv == 5
+    y = np.empty_like(x)
+    _fn("spmv_block7", dtype)(nx, ny, nz, _c(blocks, dtype), x, y)
+    return y
+
+
+def ssor_block7(b, x, blocks, omega, direction="sym", dtype=np.float64):
+    """Block SSOR half-sweeps: "fwd", "bwd" or "sym" (fwd then bwd)."""
+    b = _c(b, dtype)
+    x = np.array(x, dtype=dtype, copy=True, order="C")
+    nz, ny, nx, nv = b.shape
+    assert nv == 5
+    blk = _c(blocks, dtype)
+    if direction in ("fwd", "sym"):
+        if _fn("ssor_block7_fwd", dtype)(nx, ny, nz, blk, omega, b, x):
+            raise ZeroDivisionError("singular diagonal block")
+    if direction in ("bwd", "sym"):
+        if _fn("ssor_block7_bwd", dtype)(nx, ny, nz, blk, omega, b, x):
+            raise ZeroDivisionError("singular diagonal block")
+    if direction not in ("fwd", "bwd", "sym"):
+        raise ValueError(direction)
+    return x
+
+
+def lu5(a, dtype=np.float64):
+    lu = np.empty((5, 5), dtype)
+    piv = np.empty(5, np.int32)
+    if _fn("lu5_factor", dtype)(_c(a, dtype), lu, piv):
+        raise ZeroDivisionError("singular block")
+    return lu, piv
+
+
+# ---------------------------------------------------------------- MG
+def restrict_inject(r, az, dtype=np.float64):
+    r, az = _c(r, dtype), _c(az, dtype)
+    nz, ny, nx = r.shape
+    rc = np.empty((nz // 2, ny // 2, nx // 2), dtype)
+    _fn("restrict_inject", dtype)(nx, ny, nz, r, az, rc)
+    return rc
+
+
+def prolong_inject(zc, z, dtype=np.float64):
+    z = np.array(z, dtype=dtype, copy=True, order="C")
+    nz, ny, nx = z.shape
+    _fn("prolong_inject", dtype)(nx, ny, nz, _c(zc, dtype), z)
+    return z
+
+
+class MG:
+    """Multigrid hierarchy (kind "const27" or "var7"), levels >= 1."""
+
+    def __init__(self, kind, shape, levels, diag=26.0, off=-1.0,
+                 faces=None, dtype=np.float64):
+        self.dtype = np.dtype(dtype)
+        self.kind = {"const27": 0, "var7": 1}[kind]
+        nz, ny, nx = shape
+        self.shape = (nz, ny, nx)
+        self._keep = None
+        ptrs = (None, None, None)
+        if self.kind == 1:
+            kx, ky, kz = (_c(a, self.dtype) for a in faces)
+            self._keep = (kx, ky, kz)
+            ptrs = tuple(a.ctypes.data_as(C.c_void_p) for a in self._keep)
+        self._h = _fn("mg_create", self.dtype)(self.kind, levels, nx, ny, nz,
+                                               diag, off, *ptrs)
+        if not self._h:
+            raise ValueError("extents must be divisible by 2^(levels-1)")
+        self.levels = levels
+
+    def vcycle(self, r):
+        r = _c(r, self.dtype)
+        z = np.empty_like(r)
+        _fn("mg_vcycle", self.dtype)(self._h, r, z)
+        return z
+
+    def faces(self, level):
+        """Copies of the VAR7 face arrays of a level."""
+        nz, ny, nx = (s >> level for s in self.shape)
+        out = []
+        for axis, shp in enumerate(((nz, ny, nx + 1), (nz, ny + 1, nx),
+                                    (nz + 1, ny, nx))):
+            p = _fn("mg_faces", self.dtype)(self._h, level, axis)
+            ct = C.c_double if self.dtype == np.float64 else C.c_float
+            arr = np.ctypeslib.as_array(C.cast(p, C.POINTER(ct)),
+                                        shape=shp).copy()
+            out.append(arr)
+        return tuple(out)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _fn("mg_destroy", self.dtype)(h)
+            self._h = None
+
+
+# ---------------------------------------------------------------- PCG
+def pcg(b, x0=None, kind="const27", precond="mg", levels=4, faces=None,
+        diag=26.0, off=-1.0, max_iter=50, tol=0.0, replace_every=0):
+    """HPCG-form preconditioned CG in double.
+
+    precond: "none", "symgs", "mg" or "mg_f32" (V-cycle in float).
+    Returns dict(x, status, iters, relres, true_relres, hist)."""
+    lib = _load()
+    b = _c(b, np.float64)
+    nz, ny, nx = b.shape
+    x = (np.zeros_like(b) if x0 is None
+         else np.array(x0, dtype=np.float64, copy=True, order="C"))
+    pc = {"none": PC_NONE, "symgs": PC_SYMGS, "mg": PC_MG,
+          "mg_f32": PC_MG_F32}[precond]
+    k = {"const27": 0, "var7": 1}[kind]
+    keep = None
+    ptrs = (None, None, None)
+    if k == 1:
+        keep = tuple(_c(a, np.float64) for a in faces)
+        ptrs = tuple(a.ctypes.data_as(C.c_void_p) for a in keep)
+    it, rr, tr = C.c_int(), C.c_double(), C.c_double()
+    hist = np.zeros(max_iter + 1)
+    st = lib.m2so_pcg(k, nx, ny, nz, diag, off, *ptrs, pc, levels, b, x,
+                      max_iter, tol, replace_every, C.byref(it), C.byref(rr),
+                      C.byref(tr), hist.ctypes.data_as(C.c_void_p))
+    del keep
+    if st < 0:
+        raise ValueError("bad PCG arguments")
+    return dict(x=x, status=st, iters=it.value, relres=rr.value,
+                true_relres=tr.value, hist=hist[: it.value + 1])
