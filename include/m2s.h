@@ -1,0 +1,287 @@
+/*
+ * m2s.h -- C ABI of the MI355X-native matrix-free stencil solver library
+ * (libm2s.so): the hot path of Mat2Stencil's generated solvers, i.e. the
+ * Seidel-style sweeps with spatial loop-carried dependence (lexicographic
+ * Gauss-Seidel / SymGS and block SSOR), the Jacobi-style stencil SpMV beside
+ * them, and the multigrid-preconditioned CG around both (paper Sec. 1,
+ * Sec. 2.1.2, Sec. 4.3, Sec. 7.1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid.  A scalar field on an nx*ny*nz grid is a contiguous array stored
+ *   [nz][ny][nx] (x fastest), point p = (k*ny + j)*nx + i; this is the
+ *   paper's multi-dimensional row/column domain with the last index fastest
+ *   (Sec. 4.2.1) and its "dictionary order" of domain loops (Sec. 4.4).
+ *   "Lexicographic" = increasing p.  BLOCK7 fields carry 5 unknowns per
+ *   point ("inner value as a tensor", Sec. 4.2.3), stored [nz][ny][nx][5].
+ *   Values outside the grid are zero (Dirichlet), the padding matrix
+ *   P = [0; I; 0] of Sec. 4.1 on every axis.
+ * Memory.  Every vector / field / face-coefficient pointer is DEVICE memory
+ *   owned by the caller, contiguous, of the stencil's dtype unless stated,
+ *   and must stay valid until the stream work completes.  The library owns
+ *   only the opaque m2s_workspace / m2s_mg objects (create/destroy).
+ *   Host pointers are marked "host".
+ * Streams.  All calls are asynchronous on the given hipStream_t (0 = the
+ *   default stream) except m2s_pcg_solve, which synchronises and returns
+ *   host-side results, and the create/destroy calls.
+ * Errors.  Arguments are validated before anything is launched; a
+ *   validation error returns a status and launches nothing.  A sweep's
+ *   cross-workgroup wait is bounded: on expiry the kernel latches
+ *   M2S_ERR_TIMEOUT in the workspace error word and exits; m2s_check()
+ *   (synchronising) returns it.  No C++ exception crosses the ABI.
+ * Threading.  Calls that share a workspace or MG object must be ordered on
+ *   one stream.
+ */
+#ifndef M2S_H
+#define M2S_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    M2S_OK = 0,
+    M2S_ERR_ARG = 1,           /* null pointer, bad enum, bad option */
+    M2S_ERR_SHAPE = 2,         /* extent <= 0, not coarsenable, too large */
+    M2S_ERR_DTYPE = 3,         /* dtype not supported for this call */
+    M2S_ERR_ALIAS = 4,         /* input and output vectors overlap */
+    M2S_ERR_HIP = 5,           /* a HIP runtime call failed */
+    M2S_ERR_TIMEOUT = 6,       /* a sweep's dependency wait expired */
+    M2S_ERR_BREAKDOWN = 7,     /* CG: p.Ap <= 0 or a non-finite scalar */
+    M2S_ERR_NOT_CONVERGED = 8, /* CG: max_iter reached above tolerance */
+    M2S_ERR_UNSUPPORTED = 9    /* operator kind not valid for this call */
+} m2s_status;
+
+typedef enum { M2S_F64 = 0, M2S_F32 = 1 } m2s_dtype;
+
+/* Operator kinds.
+ * M2S_CONST27: HPCG-style 27-point operator (Sec. 7.1): `diag` on the
+ *   diagonal, `offdiag` for each of the up to 26 in-grid neighbours.
+ * M2S_VAR7: variable-coefficient diffusion D^T K D built from the
+ *   difference and padding matrices of Sec. 4.1: (A u)_p = sum over the six
+ *   faces f of p of k_f (u_p - u_q), u_q = 0 behind a boundary face.
+ *   Face arrays (device, dtype): kx [nz][ny][nx+1] (face i between points
+ *   i-1 and i), ky [nz][ny+1][nx], kz [nz+1][ny][nx].
+ * M2S_BLOCK7_5: NPB-LU-shaped 7-point stencil with 5 unknowns per point and
+ *   seven constant 5x5 blocks (host memory, 7*25 doubles, row-major, order
+ *   centre, -x, +x, -y, +y, -z, +z): (A x)_p = B0 x_p + sum_d B_d x_{p+d}.
+ *   F64 only. */
+typedef enum { M2S_CONST27 = 0, M2S_VAR7 = 1, M2S_BLOCK7_5 = 2 } m2s_kind;
+
+/* Sweep direction: forward = p ascending, backward = p descending,
+ * symmetric = forward then backward (one SymGS / one SSOR iteration). */
+typedef enum { M2S_FWD = 1, M2S_BWD = 2, M2S_SYM = 3 } m2s_dir;
+
+typedef struct {
+    int32_t nx, ny, nz;
+} m2s_extent;
+
+/* Matrix-free operator descriptor (the build's replacement for the paper's
+ * row-function SpMat, Sec. 4.2: a fixed stencil over grid extents). */
+typedef struct {
+    m2s_kind kind;
+    m2s_dtype dtype;      /* element type of vectors and face arrays */
+    m2s_extent ext;
+    double diag, offdiag; /* CONST27 only */
+    const void *kx, *ky, *kz; /* VAR7 only: device face arrays */
+    const double *blocks;     /* BLOCK7 only: HOST, 175 doubles */
+} m2s_stencil;
+
+typedef struct m2s_workspace m2s_workspace;
+typedef struct m2s_mg m2s_mg;
+
+/* Status text (static storage). */
+const char *m2s_status_string(m2s_status s);
+
+/* Library/ABI version, e.g. 10000 for 1.0.0. */
+int m2s_version(void);
+
+/* ---------------------------------------------------------------------
+ * Workspace for the dependent sweeps: per-slab progress flags (monotone
+ * epoch-tagged counters, never reset; the GPU analogue of the per-thread-
+ * pair counters that Thm. 2 of Sec. 6.1 shows are sufficient), a ticket
+ * counter that hands slabs to workgroups in dependency order, a device
+ * error word and one scratch vector of the stencil's size (the out-of-place
+ * target of a half-sweep).  Allocates device memory.  One workspace serves
+ * one extent/kind/dtype; calls using it must be stream-ordered.
+ * --------------------------------------------------------------------- */
+m2s_status m2s_workspace_create(const m2s_stencil *A, m2s_workspace **out);
+void m2s_workspace_destroy(m2s_workspace *ws);
+
+/* Synchronise `stream` and return the latched device error (M2S_OK,
+ * M2S_ERR_TIMEOUT) or M2S_ERR_HIP; clears the latch. */
+m2s_status m2s_check(m2s_workspace *ws, hipStream_t stream);
+
+/* ---------------------------------------------------------------------
+ * y = A x  (Sec. 4.3.1: sum over each row's non-zeros; Jacobi-style, no
+ * spatial dependence).  Any kind; x and y must not overlap.
+ * --------------------------------------------------------------------- */
+m2s_status m2s_spmv(const m2s_stencil *A, const void *x, void *y,
+                    hipStream_t stream);
+
+/* y = L x (part = -1) or y = U x (part = +1): the strict lower / upper
+ * triangle of A in lexicographic order.  CONST27 and VAR7.  Used by the
+ * sweep adjoint. */
+m2s_status m2s_spmv_part(const m2s_stencil *A, int part, const void *x,
+                         void *y, hipStream_t stream);
+
+/* ---------------------------------------------------------------------
+ * Gauss-Seidel sweeps in exact lexicographic order (Sec. 4.3.3, the
+ * Seidel-style routine whose domain loop reads and writes the same vector;
+ * SymGS = forward then backward, Sec. 1 and Sec. 7.1):
+ *   x_p <- (r_p - sum_{q != p} a_pq x_q) / a_pp, p ascending (FWD) or
+ *   descending (BWD), every neighbour taking its newest value.
+ * CONST27 and VAR7, F64 and F32.  x is updated in place (via the
+ * workspace's scratch vector); r is read-only; r and x must not overlap.
+ * Executed as a persistent wavefront kernel: slabs of whole planes handed
+ * to workgroups in dependency order, rows and planes inside a slab skewed
+ * on the hyperplane i + 2j + 4k (CONST27) or i + j + k (VAR7), progress
+ * flags between slabs.  The result is bitwise identical to the one-thread
+ * lexicographic sweep m2s_symgs_sequential (same per-point arithmetic).
+ * --------------------------------------------------------------------- */
+m2s_status m2s_symgs(const m2s_stencil *A, const void *r, void *x,
+                     m2s_dir dir, m2s_workspace *ws, hipStream_t stream);
+
+/* Out-of-place half-sweep: x_out = sweep(r, x_in), dir FWD or BWD only.
+ * x_in is not modified; x_in, x_out and r must not overlap. */
+m2s_status m2s_symgs_oop(const m2s_stencil *A, const void *r,
+                         const void *x_in, void *x_out, m2s_dir dir,
+                         m2s_workspace *ws, hipStream_t stream);
+
+/* Reference: the same sweep run by ONE GPU thread in plain lexicographic
+ * order, in place.  For testing the wavefront schedule only (slow). */
+m2s_status m2s_symgs_sequential(const m2s_stencil *A, const void *r,
+                                void *x, m2s_dir dir, hipStream_t stream);
+
+/* Adjoint of one Gauss-Seidel half-sweep x_new = S(r, x_old) with respect
+ * to its inputs, for a symmetric operator (CONST27, VAR7): given g = dL/dx_new
+ *   FWD: gr = (D+L)^{-T} g = (D+U)^{-1} g  (a backward sweep from zero),
+ *        gx = -U^T gr = -L gr
+ *   BWD: gr = (D+L)^{-1} g (a forward sweep from zero), gx = -U gr
+ * SYM (forward then backward) chains both in reverse order and returns the
+ * summed gr and the gradient for the sweep's starting vector.  gr and gx
+ * are outputs (overwritten); g is read-only; none may overlap.  The
+ * transposed sweeps run on the same wavefront engine in reverse order. */
+m2s_status m2s_symgs_adjoint(const m2s_stencil *A, const void *g, void *gr,
+                             void *gx, m2s_dir dir, m2s_workspace *ws,
+                             hipStream_t stream);
+
+/* ---------------------------------------------------------------------
+ * Block SSOR half-sweeps (the SSOR routine named in Sec. 1 and Sec. 4.3.3;
+ * NPB-LU shape, Sec. 7.1) for BLOCK7_5, F64:
+ *   x_p <- (1 - omega) x_p + omega B0^{-1} (b_p - sum_{d} B_d x_{p+d}),
+ * p ascending (FWD) / descending (BWD) / FWD then BWD (SYM = one SSOR
+ * iteration).  B0^{-1} is applied through an LU factorisation with partial
+ * pivoting computed once per call on the host.  x in place; b read-only.
+ * Returns M2S_ERR_ARG if B0 is singular or omega is not in (0, 2).
+ * --------------------------------------------------------------------- */
+m2s_status m2s_ssor_sweep(const m2s_stencil *A, const void *b, void *x,
+                          double omega, m2s_dir dir, m2s_workspace *ws,
+                          hipStream_t stream);
+
+/* ---------------------------------------------------------------------
+ * Multigrid V-cycle (the HPCG MG of Sec. 7.1): levels obtained by halving
+ * every extent (extents must be divisible by 2^(levels-1)); injection
+ * restriction and prolongation (coarse point I on fine point 2I, the
+ * "HPCG Prolong" matrix of Table 1); per level z = 0, one SymGS, fused
+ * residual + restriction, recurse, prolongation, one SymGS; the coarsest
+ * level runs one SymGS from zero.  CONST27 keeps the same stencil on every
+ * level; VAR7 coarse faces are the series combination of the two fine faces
+ * they span, scaled by 1/4 for the doubled spacing.
+ * prec = M2S_F32 runs the whole V-cycle in float (stored and computed):
+ * m2s_mg_vcycle then takes r and returns z in DOUBLE and converts at the
+ * boundary.  With prec = M2S_F64 r and z are double.
+ * `fine` must be CONST27 or VAR7 with dtype F64; VAR7 face arrays are read
+ * at create time only (copied/converted into library-owned storage).
+ * --------------------------------------------------------------------- */
+m2s_status m2s_mg_create(const m2s_stencil *fine, int levels, m2s_dtype prec,
+                         m2s_mg **out);
+m2s_status m2s_mg_vcycle(m2s_mg *mg, const double *r, double *z,
+                         hipStream_t stream);
+void m2s_mg_destroy(m2s_mg *mg);
+
+/* ---------------------------------------------------------------------
+ * Preconditioned CG in the HPCG form (Sec. 7.1; global scalars reduced as
+ * the DSL's reduce_add, Sec. 4.4), all CG vectors and dot products double:
+ *   r = b - A x; repeat { z = M^{-1} r; rz = r.z; p = z + (rz/rz_old) p
+ *   (p = z first); Ap = A p; alpha = rz/(p.Ap); x += alpha p;
+ *   r -= alpha Ap } until ||r||/||r0|| <= rtol.
+ * When the recursive residual passes, r is replaced by the true residual
+ * b - A x and the test repeated; replace_every > 0 also replaces it every
+ * that many iterations.  rtol <= 0 runs exactly max_iter iterations.
+ * Dot products are deterministic (fixed two-stage reduction order).
+ * A: CONST27 or VAR7, F64.  precond: NONE, SYMGS (one SymGS from zero) or
+ * MG (needs `mg` built on the same operator).  x holds x0 on entry and the
+ * solution on return.  Synchronises `stream`.  Returns M2S_OK on
+ * convergence (or after max_iter with rtol <= 0), M2S_ERR_NOT_CONVERGED,
+ * M2S_ERR_BREAKDOWN, M2S_ERR_TIMEOUT.
+ * --------------------------------------------------------------------- */
+typedef enum {
+    M2S_PC_NONE = 0,
+    M2S_PC_SYMGS = 1,
+    M2S_PC_MG = 2
+} m2s_precond;
+
+typedef struct {
+    int max_iter;
+    double rtol;
+    int replace_every;
+} m2s_pcg_opts;
+
+typedef struct {
+    int iters;
+    double rel_res;      /* ||r_k|| / ||r_0||, recursive (or replaced) */
+    double true_rel_res; /* ||b - A x|| / ||r_0||, recomputed at the end */
+    double r0_norm;
+    int status;
+    double seconds;      /* host wall time inside the call */
+} m2s_pcg_info;
+
+m2s_status m2s_pcg_solve(const m2s_stencil *A, m2s_precond precond,
+                         m2s_mg *mg, const double *b, double *x,
+                         const m2s_pcg_opts *opts, m2s_pcg_info *info,
+                         double *hist /* host, max_iter+1 or NULL */,
+                         hipStream_t stream);
+
+/* ---------------------------------------------------------------------
+ * Gradient with respect to the VAR7 face coefficients of a loss whose
+ * derivative with respect to the solution u of A(k) u = f has adjoint
+ * lam = A^{-T} dL/du:  dL/dk_f = -(lam_p - lam_q)(u_p - u_q), zero ghosts.
+ * Outputs have the face-array shapes; F64.
+ * --------------------------------------------------------------------- */
+m2s_status m2s_face_grad(const m2s_stencil *A, const double *u,
+                         const double *lam, double *gkx, double *gky,
+                         double *gkz, hipStream_t stream);
+
+/* ---------------------------------------------------------------------
+ * Small vector kernels used around the solvers (double, device):
+ * m2s_dot writes x.y (fixed-order two-stage reduction) to *out (device).
+ * m2s_convert copies n elements between F64 and F32 (round to nearest).
+ * --------------------------------------------------------------------- */
+m2s_status m2s_dot(const double *x, const double *y, int64_t n, double *out,
+                   hipStream_t stream);
+m2s_status m2s_convert(const void *src, m2s_dtype src_t, void *dst,
+                       m2s_dtype dst_t, int64_t n, hipStream_t stream);
+
+/* ---------------------------------------------------------------------
+ * Schedule of the wavefront sweep (host only, no GPU needed): the slab
+ * thickness in planes, number of slabs, row slots per plane (threads per
+ * plane in a workgroup), the per-row and per-plane skew of the hyperplane
+ * and the number of local steps of a full slab.  Exposed so the schedule's
+ * legality (every dependence from a strictly earlier step) can be checked
+ * on the CPU.
+ * --------------------------------------------------------------------- */
+typedef struct {
+    int32_t slab_planes, nslabs, row_slots, lag_row, lag_plane, steps;
+    int32_t threads, publish_every;
+} m2s_sweep_plan;
+
+m2s_status m2s_plan_sweep(const m2s_stencil *A, m2s_sweep_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* M2S_H */

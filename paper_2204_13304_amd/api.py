@@ -1,0 +1,376 @@
+"""Torch-facing binding of libm2s.so.
+
+Every function marshals torch tensors (device memory, current HIP stream)
+into the C ABI of include/m2s.h; every arithmetic step runs in the HIP
+kernels.  Tensors must be contiguous, on the GPU and of the stencil's dtype;
+otherwise TypeError / ValueError is raised before anything is launched.
+
+Fields are shaped (nz, ny, nx) (x fastest), BLOCK7 fields (nz, ny, nx, 5);
+VAR7 face arrays kx (nz, ny, nx+1), ky (nz, ny+1, nx), kz (nz+1, ny, nx).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float64: L.F64, torch.float32: L.F32}
+_DIRS = {"fwd": L.FWD, "bwd": L.BWD, "sym": L.SYM}
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(None)
+
+
+def _need(t, dtype, shape, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU, got {t.device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got "
+                         f"{tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Stencil:
+    """Matrix-free operator descriptor (m2s_stencil)."""
+
+    def __init__(self, kind, shape, dtype=torch.float64, diag=26.0, off=-1.0,
+                 faces=None, blocks=None):
+        self.kind = kind
+        self.shape = tuple(int(s) for s in shape)
+        self.dtype = dtype
+        if dtype not in _DT:
+            raise TypeError("dtype must be torch.float64 or torch.float32")
+        self.diag, self.off = float(diag), float(off)
+        self.faces = faces
+        self.blocks = None
+        nz, ny, nx = self.shape
+        if kind == L.VAR7:
+            kx, ky, kz = faces
+            _need(kx, dtype, (nz, ny, nx + 1), "kx")
+            _need(ky, dtype, (nz, ny + 1, nx), "ky")
+            _need(kz, dtype, (nz + 1, ny, nx), "kz")
+        if kind == L.BLOCK7_5:
+            if dtype != torch.float64:
+                raise TypeError("BLOCK7 is float64 only")
+            b = np.ascontiguousarray(np.asarray(blocks, dtype=np.float64))
+            if b.shape != (7, 5, 5):
+                raise ValueError("blocks must have shape (7, 5, 5)")
+            self.blocks = b
+        self._c = self._make_c()
+
+    def _make_c(self):
+        nz, ny, nx = self.shape
+        s = L.StencilC()
+        s.kind = self.kind
+        s.dtype = _DT[self.dtype]
+        s.ext = L.Extent(nx, ny, nz)
+        s.diag, s.offdiag = self.diag, self.off
+        if self.kind == L.VAR7:
+            s.kx, s.ky, s.kz = (t.data_ptr() for t in self.faces)
+        if self.kind == L.BLOCK7_5:
+            s.blocks = self.blocks.ctypes.data
+        return s
+
+    @property
+    def field_shape(self):
+        return self.shape + ((5,) if self.kind == L.BLOCK7_5 else ())
+
+    def ref(self):
+        return C.byref(self._c)
+
+    def with_dtype(self, dtype):
+        faces = None
+        if self.kind == L.VAR7:
+            faces = tuple(f.to(dtype).contiguous() for f in self.faces)
+        return Stencil(self.kind, self.shape, dtype, self.diag, self.off,
+                       faces, self.blocks)
+
+
+def const27(shape, dtype=torch.float64, diag=26.0, off=-1.0):
+    return Stencil(L.CONST27, shape, dtype, diag, off)
+
+
+def var7(kx, ky, kz):
+    nz, ny, nx1 = kx.shape
+    return Stencil(L.VAR7, (nz, ny, nx1 - 1), kx.dtype,
+                   faces=(kx.contiguous(), ky.contiguous(), kz.contiguous()))
+
+
+def block7(shape, blocks):
+    return Stencil(L.BLOCK7_5, shape, torch.float64, blocks=blocks)
+
+
+class Workspace:
+    def __init__(self, A: Stencil):
+        lib = L.load()
+        self.A = A
+        h = C.c_void_p()
+        L.check(lib.m2s_workspace_create(A.ref(), C.byref(h)),
+                "m2s_workspace_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def check(self):
+        L.check(L.load().m2s_check(self._h, _stream()), "m2s_check")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            L.load().m2s_workspace_destroy(h)
+            self._h = None
+
+
+def spmv(A: Stencil, x, y=None):
+    lib = L.load()
+    _need(x, A.dtype, A.field_shape, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    _need(y, A.dtype, A.field_shape, "y")
+    L.check(lib.m2s_spmv(A.ref(), _ptr(x), _ptr(y), _stream()), "m2s_spmv")
+    return y
+
+
+def spmv_part(A: Stencil, x, part, y=None):
+    lib = L.load()
+    _need(x, A.dtype, A.field_shape, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    L.check(lib.m2s_spmv_part(A.ref(), int(part), _ptr(x), _ptr(y),
+                              _stream()), "m2s_spmv_part")
+    return y
+
+
+def symgs(A: Stencil, r, x, direction="sym", ws: Workspace | None = None):
+    """In-place exact lexicographic Gauss-Seidel sweep(s) on x."""
+    lib = L.load()
+    _need(r, A.dtype, A.field_shape, "r")
+    _need(x, A.dtype, A.field_shape, "x")
+    ws = ws or Workspace(A)
+    L.check(lib.m2s_symgs(A.ref(), _ptr(r), _ptr(x), _DIRS[direction],
+                          ws.handle, _stream()), "m2s_symgs")
+    return x
+
+
+def symgs_oop(A: Stencil, r, x_in, x_out, direction="fwd",
+              ws: Workspace | None = None):
+    lib = L.load()
+    _need(r, A.dtype, A.field_shape, "r")
+    if x_in is not None:
+        _need(x_in, A.dtype, A.field_shape, "x_in")
+    _need(x_out, A.dtype, A.field_shape, "x_out")
+    ws = ws or Workspace(A)
+    L.check(lib.m2s_symgs_oop(A.ref(), _ptr(r), _ptr(x_in), _ptr(x_out),
+                              _DIRS[direction], ws.handle, _stream()),
+            "m2s_symgs_oop")
+    return x_out
+
+
+def symgs_sequential(A: Stencil, r, x, direction="sym"):
+    lib = L.load()
+    _need(r, A.dtype, A.field_shape, "r")
+    _need(x, A.dtype, A.field_shape, "x")
+    L.check(lib.m2s_symgs_sequential(A.ref(), _ptr(r), _ptr(x),
+                                     _DIRS[direction], _stream()),
+            "m2s_symgs_sequential")
+    return x
+
+
+def symgs_adjoint(A: Stencil, g, direction="fwd", ws: Workspace | None = None):
+    """(gr, gx): gradients of <g, sweep(r, x)> w.r.t. r and x."""
+    lib = L.load()
+    _need(g, A.dtype, A.field_shape, "g")
+    gr, gx = torch.empty_like(g), torch.empty_like(g)
+    ws = ws or Workspace(A)
+    L.check(lib.m2s_symgs_adjoint(A.ref(), _ptr(g), _ptr(gr), _ptr(gx),
+                                  _DIRS[direction], ws.handle, _stream()),
+            "m2s_symgs_adjoint")
+    return gr, gx
+
+
+def ssor_sweep(A: Stencil, b, x, omega, direction="sym",
+               ws: Workspace | None = None):
+    lib = L.load()
+    _need(b, A.dtype, A.field_shape, "b")
+    _need(x, A.dtype, A.field_shape, "x")
+    ws = ws or Workspace(A)
+    L.check(lib.m2s_ssor_sweep(A.ref(), _ptr(b), _ptr(x), float(omega),
+                               _DIRS[direction], ws.handle, _stream()),
+            "m2s_ssor_sweep")
+    return x
+
+
+class MG:
+    """Multigrid hierarchy; prec torch.float64 or torch.float32."""
+
+    def __init__(self, A: Stencil, levels=4, prec=torch.float64):
+        lib = L.load()
+        self.A = A
+        h = C.c_void_p()
+        L.check(lib.m2s_mg_create(A.ref(), int(levels), _DT[prec],
+                                  C.byref(h)), "m2s_mg_create")
+        self._h = h
+        self.levels = levels
+        self.prec = prec
+
+    @property
+    def handle(self):
+        return self._h
+
+    def vcycle(self, r, z=None):
+        lib = L.load()
+        _need(r, torch.float64, self.A.shape, "r")
+        if z is None:
+            z = torch.empty_like(r)
+        L.check(lib.m2s_mg_vcycle(self._h, _ptr(r), _ptr(z), _stream()),
+                "m2s_mg_vcycle")
+        return z
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            L.load().m2s_mg_destroy(h)
+            self._h = None
+
+
+def pcg_solve(A: Stencil, b, x=None, precond="mg", mg: MG | None = None,
+              max_iter=50, rtol=0.0, replace_every=0, history=False,
+              raise_on_error=True):
+    """HPCG-form PCG; returns (x, info dict)."""
+    lib = L.load()
+    _need(b, torch.float64, A.shape, "b")
+    if x is None:
+        x = torch.zeros_like(b)
+    _need(x, torch.float64, A.shape, "x")
+    pc = {"none": L.PC_NONE, "symgs": L.PC_SYMGS, "mg": L.PC_MG}[precond]
+    opts = L.PcgOpts(int(max_iter), float(rtol), int(replace_every))
+    info = L.PcgInfo()
+    hist = np.zeros(max_iter + 1) if history else None
+    st = lib.m2s_pcg_solve(A.ref(), pc, mg.handle if mg else None, _ptr(b),
+                           _ptr(x), C.byref(opts), C.byref(info),
+                           hist.ctypes.data_as(C.c_void_p) if history
+                           else None, _stream())
+    out = dict(status=L.STATUS.get(st, st), iters=info.iters,
+               rel_res=info.rel_res, true_rel_res=info.true_rel_res,
+               r0_norm=info.r0_norm, seconds=info.seconds)
+    if history:
+        out["hist"] = hist[: info.iters + 1]
+    if raise_on_error and st not in (L.M2S_OK,):
+        raise L.M2SError(st, "m2s_pcg_solve")
+    return x, out
+
+
+def face_grad(A: Stencil, u, lam):
+    lib = L.load()
+    nz, ny, nx = A.shape
+    _need(u, torch.float64, A.shape, "u")
+    _need(lam, torch.float64, A.shape, "lam")
+    opts = dict(dtype=torch.float64, device=u.device)
+    gx = torch.empty((nz, ny, nx + 1), **opts)
+    gy = torch.empty((nz, ny + 1, nx), **opts)
+    gz = torch.empty((nz + 1, ny, nx), **opts)
+    L.check(lib.m2s_face_grad(A.ref(), _ptr(u), _ptr(lam), _ptr(gx),
+                              _ptr(gy), _ptr(gz), _stream()), "m2s_face_grad")
+    return gx, gy, gz
+
+
+def dot(x, y):
+    lib = L.load()
+    if x.dtype != torch.float64 or y.dtype != torch.float64:
+        raise TypeError("dot takes float64 tensors")
+    if x.numel() != y.numel() or not x.is_contiguous() or \
+            not y.is_contiguous():
+        raise ValueError("dot needs contiguous tensors of equal size")
+    out = torch.empty((), dtype=torch.float64, device=x.device)
+    L.check(lib.m2s_dot(_ptr(x), _ptr(y), x.numel(), _ptr(out), _stream()),
+            "m2s_dot")
+    return out
+
+
+def convert(src, dtype):
+    lib = L.load()
+    dst = torch.empty(src.shape, dtype=dtype, device=src.device)
+    L.check(lib.m2s_convert(_ptr(src), _DT[src.dtype], _ptr(dst), _DT[dtype],
+                            src.numel(), _stream()), "m2s_convert")
+    return dst
+
+
+def plan_sweep(A: Stencil):
+    """Host-only schedule of the wavefront sweep (no GPU needed)."""
+    lib = L.load()
+    p = L.SweepPlanC()
+    L.check(lib.m2s_plan_sweep(A.ref(), C.byref(p)), "m2s_plan_sweep")
+    return {f: getattr(p, f) for f, _ in L.SweepPlanC._fields_}
+
+
+# --------------------------------------------------------------------------
+# Autograd.
+# --------------------------------------------------------------------------
+class SolveFn(torch.autograd.Function):
+    """u = A(k)^{-1} f by MG-PCG on the VAR7 operator.  Backward: one adjoint
+    MG-PCG solve A^T lam = du (A symmetric) and the face-gradient kernel:
+    df = lam, dk_f = -(lam_p - lam_q)(u_p - u_q)."""
+
+    @staticmethod
+    def forward(ctx, kx, ky, kz, f, levels, rtol, max_iter):
+        A = var7(kx, ky, kz)
+        mg = MG(A, levels)
+        u, info = pcg_solve(A, f.contiguous(), None, "mg", mg,
+                            max_iter=max_iter, rtol=rtol)
+        ctx.save_for_backward(kx, ky, kz, u)
+        ctx.cfg = (levels, rtol, max_iter)
+        ctx.info = info
+        return u
+
+    @staticmethod
+    def backward(ctx, gu):
+        kx, ky, kz, u = ctx.saved_tensors
+        levels, rtol, max_iter = ctx.cfg
+        A = var7(kx, ky, kz)
+        mg = MG(A, levels)
+        lam, _ = pcg_solve(A, gu.contiguous(), None, "mg", mg,
+                           max_iter=max_iter, rtol=rtol)
+        gx, gy, gz = face_grad(A, u, lam)
+        return gx, gy, gz, lam, None, None, None
+
+
+def solve(kx, ky, kz, f, levels=3, rtol=1e-10, max_iter=200):
+    return SolveFn.apply(kx, ky, kz, f, levels, rtol, max_iter)
+
+
+class SymGSFn(torch.autograd.Function):
+    """x_new = sweep(r, x_old) for a symmetric stencil (CONST27 / VAR7 with
+    fixed coefficients).  Backward: the transposed sweeps in reverse order
+    (m2s_symgs_adjoint)."""
+
+    @staticmethod
+    def forward(ctx, r, x, A, direction):
+        ctx.A, ctx.direction = A, direction
+        out = x.detach().clone()
+        symgs(A, r.detach().contiguous(), out, direction)
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        gr, gx = symgs_adjoint(ctx.A, g.contiguous(), ctx.direction)
+        return gr, gx, None, None
+
+
+def symgs_fn(A, r, x, direction="sym"):
+    return SymGSFn.apply(r, x, A, direction)

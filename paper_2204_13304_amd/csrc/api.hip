@@ -1,0 +1,845 @@
+// api.hip -- host side of libm2s.so: the extern "C" entry points declared in
+// include/m2s.h.  Validates arguments, plans the wavefront sweep, owns the
+// workspace and multigrid objects, and drives the PCG loop.  Every
+// arithmetic step runs in the HIP kernels of k_sweep.hip / k_ops.hip.
+#include "m2s_internal.hpp"
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace m2s;
+
+namespace m2s {
+hipError_t launch_sweep_sequential_b7(const m2s_stencil &A,
+                                      const Block7Consts &b7, double omega,
+                                      const void *b, void *x, bool bwd,
+                                      hipStream_t s);
+int sweep_max_blocks_per_cu(m2s_kind kind, m2s_dtype t, int threads);
+
+// LU with partial pivoting of the 5x5 centre block (row-major), host side.
+hipError_t fill_block7_consts(const double *blocks, Block7Consts &C)
+{
+    if (!blocks) return hipErrorInvalidValue;
+    for (int d = 0; d < 7; ++d)
+        for (int e = 0; e < 25; ++e) C.B[d][e] = blocks[25 * d + e];
+    double a[25];
+    for (int e = 0; e < 25; ++e) a[e] = blocks[e];
+    for (int c = 0; c < 5; ++c) {
+        int p = c;
+        double best = std::fabs(a[5 * c + c]);
+        for (int r = c + 1; r < 5; ++r)
+            if (std::fabs(a[5 * r + c]) > best) {
+                best = std::fabs(a[5 * r + c]);
+                p = r;
+            }
+        if (!(best > 0.0) || !std::isfinite(best)) return hipErrorInvalidValue;
+        C.piv[c] = p;
+        if (p != c)
+            for (int t = 0; t < 5; ++t) std::swap(a[5 * c + t], a[5 * p + t]);
+        for (int r = c + 1; r < 5; ++r) {
+            a[5 * r + c] /= a[5 * c + c];
+            for (int t = c + 1; t < 5; ++t)
+                a[5 * r + t] -= a[5 * r + c] * a[5 * c + t];
+        }
+    }
+    for (int e = 0; e < 25; ++e) C.lu[e] = a[e];
+    for (int c = 0; c < 5; ++c) C.inv_udiag[c] = 1.0 / a[5 * c + c];
+    return hipSuccess;
+}
+}  // namespace m2s
+
+struct m2s_workspace : public Workspace {};
+
+namespace {
+
+constexpr int kMaxThreads = 1024;
+
+int env_int(const char *name, int dflt)
+{
+    const char *e = getenv(name);
+    return e ? atoi(e) : dflt;
+}
+
+size_t elem_size(const m2s_stencil &A)
+{
+    size_t e = A.dtype == M2S_F64 ? 8 : 4;
+    return A.kind == M2S_BLOCK7_5 ? 5 * e : e;
+}
+
+int64_t npoints(const m2s_stencil &A)
+{
+    return (int64_t)A.ext.nx * A.ext.ny * A.ext.nz;
+}
+
+m2s_status validate(const m2s_stencil *A)
+{
+    if (!A) return M2S_ERR_ARG;
+    if (A->kind != M2S_CONST27 && A->kind != M2S_VAR7 &&
+        A->kind != M2S_BLOCK7_5)
+        return M2S_ERR_ARG;
+    if (A->dtype != M2S_F64 && A->dtype != M2S_F32) return M2S_ERR_DTYPE;
+    if (A->ext.nx <= 0 || A->ext.ny <= 0 || A->ext.nz <= 0)
+        return M2S_ERR_SHAPE;
+    if (npoints(*A) > ((int64_t)1 << 40)) return M2S_ERR_SHAPE;
+    if (A->kind == M2S_VAR7 && (!A->kx || !A->ky || !A->kz))
+        return M2S_ERR_ARG;
+    if (A->kind == M2S_BLOCK7_5) {
+        if (A->dtype != M2S_F64) return M2S_ERR_DTYPE;
+        if (!A->blocks) return M2S_ERR_ARG;
+    }
+    if (A->kind == M2S_CONST27 && !(A->diag != 0.0 && std::isfinite(A->diag)))
+        return M2S_ERR_ARG;
+    return M2S_OK;
+}
+
+bool overlap(const void *a, const void *b, size_t bytes)
+{
+    if (!a || !b) return false;
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + bytes && y < x + bytes;
+}
+
+m2s_status hip_status(hipError_t e)
+{
+    return e == hipSuccess ? M2S_OK : M2S_ERR_HIP;
+}
+
+#define M2S_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return M2S_ERR_HIP;       \
+    } while (0)
+
+// The wavefront schedule.  Row j of local plane kk of a slab processes
+// column i at local step i + LJ*j + LK*kk; a thread owns the rows
+// j = s, s+R, s+2R, ... of one plane, which never overlap in time because
+// LJ*R >= nx.
+m2s_status make_plan(const m2s_stencil &A, SweepPlan &P, bool with_grid)
+{
+    const int nx = A.ext.nx, ny = A.ext.ny, nz = A.ext.nz;
+    const bool c27 = A.kind == M2S_CONST27;
+    P.lag_row = c27 ? 2 : 1;
+    P.lag_plane = c27 ? 4 : 1;
+    P.halo_x = c27 ? 1 : 0;
+    P.halo_y = c27 ? 1 : 0;
+    int R = (nx + P.lag_row - 1) / P.lag_row;
+    if (R > ny) R = ny;
+    if (R > kMaxThreads) return M2S_ERR_SHAPE;
+    P.row_slots = R;
+    int bk = env_int("M2S_SLAB_PLANES", 0);
+    if (bk <= 0) {
+        // default thickness: enough rows per workgroup to fill a CU without
+        // serialising too much of the plane chain on one workgroup
+        const int target_threads = A.kind == M2S_BLOCK7_5 ? 256 : 512;
+        bk = target_threads / R;
+        if (bk < 1) bk = 1;
+        if (bk > 8) bk = 8;
+    }
+    if (bk * R > kMaxThreads) bk = kMaxThreads / R;
+    if (bk > nz) bk = nz;
+    if (bk < 1) bk = 1;
+    P.slab_planes = bk;
+    P.nslabs = (nz + bk - 1) / bk;
+    P.threads = ((bk * R + 63) / 64) * 64;
+    P.publish_every = env_int("M2S_PUBLISH_EVERY", 4);
+    if (P.publish_every < 1) P.publish_every = 1;
+    P.grid = 0;
+    if (with_grid) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return M2S_ERR_HIP;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                  dev) != hipSuccess)
+            return M2S_ERR_HIP;
+        int per_cu = sweep_max_blocks_per_cu(A.kind, A.dtype, P.threads);
+        int64_t cap = (int64_t)cus * per_cu;
+        P.grid = (int)std::min<int64_t>(P.nslabs, cap);
+        if (P.grid < 1) P.grid = 1;
+    }
+    return M2S_OK;
+}
+
+m2s_status check_ws(const m2s_stencil &A, const m2s_workspace *ws)
+{
+    if (!ws) return M2S_ERR_ARG;
+    if (ws->kind != A.kind || ws->dtype != A.dtype || ws->g.nx != A.ext.nx ||
+        ws->g.ny != A.ext.ny || ws->g.nz != A.ext.nz)
+        return M2S_ERR_SHAPE;
+    return M2S_OK;
+}
+
+// One half-sweep out of place.
+m2s_status half_sweep(const m2s_stencil &A, const Block7Consts *b7,
+                      double omega, const void *r, const void *xin,
+                      void *xout, bool bwd, bool zero_init,
+                      m2s_workspace *ws, hipStream_t s)
+{
+    SweepPlan P{};
+    m2s_status st = make_plan(A, P, true);
+    if (st != M2S_OK) return st;
+    if (P.nslabs > ws->nflags) return M2S_ERR_SHAPE;
+    return hip_status(launch_sweep(A, b7, omega, r, xin, xout, bwd, zero_init,
+                                   *ws, P, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *m2s_status_string(m2s_status s)
+{
+    switch (s) {
+    case M2S_OK: return "ok";
+    case M2S_ERR_ARG: return "invalid argument";
+    case M2S_ERR_SHAPE: return "invalid or unsupported shape";
+    case M2S_ERR_DTYPE: return "unsupported dtype";
+    case M2S_ERR_ALIAS: return "input and output overlap";
+    case M2S_ERR_HIP: return "HIP runtime error";
+    case M2S_ERR_TIMEOUT: return "sweep dependency wait timed out";
+    case M2S_ERR_BREAKDOWN: return "CG breakdown";
+    case M2S_ERR_NOT_CONVERGED: return "CG did not converge";
+    case M2S_ERR_UNSUPPORTED: return "operator kind not supported here";
+    }
+    return "unknown status";
+}
+
+int m2s_version(void) { return 10000; }
+
+m2s_status m2s_plan_sweep(const m2s_stencil *A, m2s_sweep_plan *plan)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (!plan) return M2S_ERR_ARG;
+    SweepPlan P{};
+    st = make_plan(*A, P, false);
+    if (st != M2S_OK) return st;
+    plan->slab_planes = P.slab_planes;
+    plan->nslabs = P.nslabs;
+    plan->row_slots = P.row_slots;
+    plan->lag_row = P.lag_row;
+    plan->lag_plane = P.lag_plane;
+    plan->steps = A->ext.nx + P.lag_row * (A->ext.ny - 1) +
+                  P.lag_plane * (P.slab_planes - 1);
+    plan->threads = P.threads;
+    plan->publish_every = P.publish_every;
+    return M2S_OK;
+}
+
+m2s_status m2s_workspace_create(const m2s_stencil *A, m2s_workspace **out)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (!out) return M2S_ERR_ARG;
+    *out = nullptr;
+    m2s_workspace *ws = new (std::nothrow) m2s_workspace();
+    if (!ws) return M2S_ERR_HIP;
+    std::memset((Workspace *)ws, 0, sizeof(Workspace));
+    ws->kind = A->kind;
+    ws->dtype = A->dtype;
+    ws->g = Grid{A->ext.nx, A->ext.ny, A->ext.nz};
+    if (hipGetDevice(&ws->dev) != hipSuccess) { delete ws; return M2S_ERR_HIP; }
+    ws->nflags = A->ext.nz;
+    const size_t vb = (size_t)npoints(*A) * elem_size(*A);
+    bool ok = hipMalloc(&ws->flags, sizeof(uint64_t) * ws->nflags) ==
+                  hipSuccess &&
+              hipMalloc(&ws->ticket, sizeof(uint64_t)) == hipSuccess &&
+              hipMalloc(&ws->err, sizeof(int)) == hipSuccess &&
+              hipMalloc(&ws->scratch, vb) == hipSuccess &&
+              hipMalloc(&ws->scratch2, vb) == hipSuccess;
+    ok = ok && hipMemset(ws->flags, 0, sizeof(uint64_t) * ws->nflags) ==
+                   hipSuccess &&
+         hipMemset(ws->ticket, 0, sizeof(uint64_t)) == hipSuccess &&
+         hipMemset(ws->err, 0, sizeof(int)) == hipSuccess &&
+         hipDeviceSynchronize() == hipSuccess;
+    if (!ok) {
+        m2s_workspace_destroy(ws);
+        return M2S_ERR_HIP;
+    }
+    *out = ws;
+    return M2S_OK;
+}
+
+void m2s_workspace_destroy(m2s_workspace *ws)
+{
+    if (!ws) return;
+    (void)hipDeviceSynchronize();
+    if (ws->flags) (void)hipFree(ws->flags);
+    if (ws->ticket) (void)hipFree(ws->ticket);
+    if (ws->err) (void)hipFree(ws->err);
+    if (ws->scratch) (void)hipFree(ws->scratch);
+    if (ws->scratch2) (void)hipFree(ws->scratch2);
+    delete ws;
+}
+
+m2s_status m2s_check(m2s_workspace *ws, hipStream_t stream)
+{
+    if (!ws) return M2S_ERR_ARG;
+    if (hipStreamSynchronize(stream) != hipSuccess) return M2S_ERR_HIP;
+    int e = 0;
+    if (hipMemcpy(&e, ws->err, sizeof(int), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return M2S_ERR_HIP;
+    if (e) {
+        // an aborted sweep leaves the ticket counter ahead of the host's
+        // bookkeeping: resynchronise it before the workspace is reused
+        uint64_t tk = 0;
+        if (hipMemcpy(&tk, ws->ticket, sizeof(tk), hipMemcpyDeviceToHost) !=
+                hipSuccess ||
+            hipMemset(ws->err, 0, sizeof(int)) != hipSuccess)
+            return M2S_ERR_HIP;
+        if (hipDeviceSynchronize() != hipSuccess) return M2S_ERR_HIP;
+        ws->ticket_base = tk;
+        return M2S_ERR_TIMEOUT;
+    }
+    return M2S_OK;
+}
+
+m2s_status m2s_spmv(const m2s_stencil *A, const void *x, void *y,
+                    hipStream_t stream)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (!x || !y) return M2S_ERR_ARG;
+    const size_t vb = (size_t)npoints(*A) * elem_size(*A);
+    if (overlap(x, y, vb)) return M2S_ERR_ALIAS;
+    return hip_status(launch_spmv(*A, x, y, stream));
+}
+
+m2s_status m2s_spmv_part(const m2s_stencil *A, int part, const void *x,
+                         void *y, hipStream_t stream)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (A->kind == M2S_BLOCK7_5) return M2S_ERR_UNSUPPORTED;
+    if (!x || !y || (part != -1 && part != 1)) return M2S_ERR_ARG;
+    const size_t vb = (size_t)npoints(*A) * elem_size(*A);
+    if (overlap(x, y, vb)) return M2S_ERR_ALIAS;
+    return hip_status(launch_spmv_part(*A, part, x, y, stream));
+}
+
+m2s_status m2s_symgs_oop(const m2s_stencil *A, const void *r,
+                         const void *x_in, void *x_out, m2s_dir dir,
+                         m2s_workspace *ws, hipStream_t stream)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (A->kind == M2S_BLOCK7_5) return M2S_ERR_UNSUPPORTED;
+    if (!r || !x_out) return M2S_ERR_ARG;
+    if (dir != M2S_FWD && dir != M2S_BWD) return M2S_ERR_ARG;
+    if ((st = check_ws(*A, ws)) != M2S_OK) return st;
+    const size_t vb = (size_t)npoints(*A) * elem_size(*A);
+    if (overlap(r, x_out, vb) || overlap(x_in, x_out, vb)) return M2S_ERR_ALIAS;
+    return half_sweep(*A, nullptr, 1.0, r, x_in, x_out, dir == M2S_BWD,
+                      x_in == nullptr, ws, stream);
+}
+
+m2s_status m2s_symgs(const m2s_stencil *A, const void *r, void *x,
+                     m2s_dir dir, m2s_workspace *ws, hipStream_t stream)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (A->kind == M2S_BLOCK7_5) return M2S_ERR_UNSUPPORTED;
+    if (!r || !x) return M2S_ERR_ARG;
+    if (dir != M2S_FWD && dir != M2S_BWD && dir != M2S_SYM) return M2S_ERR_ARG;
+    if ((st = check_ws(*A, ws)) != M2S_OK) return st;
+    const size_t vb = (size_t)npoints(*A) * elem_size(*A);
+    if (overlap(r, x, vb)) return M2S_ERR_ALIAS;
+    if (dir == M2S_SYM) {
+        if ((st = half_sweep(*A, nullptr, 1.0, r, x, ws->scratch, false,
+                             false, ws, stream)) != M2S_OK)
+            return st;
+        return half_sweep(*A, nullptr, 1.0, r, ws->scratch, x, true, false,
+                          ws, stream);
+    }
+    if ((st = half_sweep(*A, nullptr, 1.0, r, x, ws->scratch,
+                         dir == M2S_BWD, false, ws, stream)) != M2S_OK)
+        return st;
+    return hip_status(launch_copy(x, ws->scratch, (int64_t)vb, stream));
+}
+
+m2s_status m2s_symgs_sequential(const m2s_stencil *A, const void *r, void *x,
+                                m2s_dir dir, hipStream_t stream)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (!r || !x) return M2S_ERR_ARG;
+    if (dir != M2S_FWD && dir != M2S_BWD && dir != M2S_SYM) return M2S_ERR_ARG;
+    if (A->kind == M2S_BLOCK7_5) return M2S_ERR_UNSUPPORTED;
+    const size_t vb = (size_t)npoints(*A) * elem_size(*A);
+    if (overlap(r, x, vb)) return M2S_ERR_ALIAS;
+    if (dir & M2S_FWD)
+        M2S_TRY(launch_sweep_sequential(*A, r, x, false, stream));
+    if (dir & M2S_BWD)
+        M2S_TRY(launch_sweep_sequential(*A, r, x, true, stream));
+    return M2S_OK;
+}
+
+m2s_status m2s_symgs_adjoint(const m2s_stencil *A, const void *g, void *gr,
+                             void *gx, m2s_dir dir, m2s_workspace *ws,
+                             hipStream_t stream)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (A->kind == M2S_BLOCK7_5) return M2S_ERR_UNSUPPORTED;
+    if (!g || !gr || !gx) return M2S_ERR_ARG;
+    if (dir != M2S_FWD && dir != M2S_BWD && dir != M2S_SYM) return M2S_ERR_ARG;
+    if ((st = check_ws(*A, ws)) != M2S_OK) return st;
+    const size_t vb = (size_t)npoints(*A) * elem_size(*A);
+    if (overlap(g, gr, vb) || overlap(g, gx, vb) || overlap(gr, gx, vb))
+        return M2S_ERR_ALIAS;
+    const m2s_dtype t = A->dtype;
+    const int64_t n = npoints(*A);
+    if (dir == M2S_FWD) {
+        // gr = (D+U)^{-1} g: backward sweep from zero with right side g
+        if ((st = half_sweep(*A, nullptr, 1.0, g, nullptr, gr, true, true, ws,
+                             stream)) != M2S_OK)
+            return st;
+        M2S_TRY(launch_spmv_part(*A, -1, gr, gx, stream));
+        return hip_status(launch_scale(gx, t, n, -1.0, stream));
+    }
+    if (dir == M2S_BWD) {
+        if ((st = half_sweep(*A, nullptr, 1.0, g, nullptr, gr, false, true,
+                             ws, stream)) != M2S_OK)
+            return st;
+        M2S_TRY(launch_spmv_part(*A, +1, gr, gx, stream));
+        return hip_status(launch_scale(gx, t, n, -1.0, stream));
+    }
+    // SYM: x1 = F(r, x0), x2 = B(r, x1).  Reverse order:
+    //   y2 = (D+L)^{-1} g ; g1 = -U y2 ; y1 = (D+U)^{-1} g1 ; gr = y2 + y1 ;
+    //   gx0 = -L y1
+    void *y2 = ws->scratch2;
+    if ((st = half_sweep(*A, nullptr, 1.0, g, nullptr, y2, false, true, ws,
+                         stream)) != M2S_OK)
+        return st;
+    M2S_TRY(launch_spmv_part(*A, +1, y2, gx, stream));
+    M2S_TRY(launch_scale(gx, t, n, -1.0, stream));  // gx holds g1
+    if ((st = half_sweep(*A, nullptr, 1.0, gx, nullptr, gr, true, true, ws,
+                         stream)) != M2S_OK)
+        return st;  // gr holds y1
+    M2S_TRY(launch_spmv_part(*A, -1, gr, gx, stream));
+    M2S_TRY(launch_scale(gx, t, n, -1.0, stream));
+    // gr = y1 + y2
+    return hip_status(launch_add(gr, y2, t, n, stream));
+}
+
+m2s_status m2s_ssor_sweep(const m2s_stencil *A, const void *b, void *x,
+                          double omega, m2s_dir dir, m2s_workspace *ws,
+                          hipStream_t stream)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (A->kind != M2S_BLOCK7_5) return M2S_ERR_UNSUPPORTED;
+    if (!b || !x) return M2S_ERR_ARG;
+    if (!(omega > 0.0 && omega < 2.0)) return M2S_ERR_ARG;
+    if (dir != M2S_FWD && dir != M2S_BWD && dir != M2S_SYM) return M2S_ERR_ARG;
+    if ((st = check_ws(*A, ws)) != M2S_OK) return st;
+    const size_t vb = (size_t)npoints(*A) * elem_size(*A);
+    if (overlap(b, x, vb)) return M2S_ERR_ALIAS;
+    Block7Consts C{};
+    if (fill_block7_consts(A->blocks, C) != hipSuccess) return M2S_ERR_ARG;
+    if (dir == M2S_SYM) {
+        if ((st = half_sweep(*A, &C, omega, b, x, ws->scratch, false, false,
+                             ws, stream)) != M2S_OK)
+            return st;
+        return half_sweep(*A, &C, omega, b, ws->scratch, x, true, false, ws,
+                          stream);
+    }
+    if ((st = half_sweep(*A, &C, omega, b, x, ws->scratch, dir == M2S_BWD,
+                         false, ws, stream)) != M2S_OK)
+        return st;
+    return hip_status(launch_copy(x, ws->scratch, (int64_t)vb, stream));
+}
+
+m2s_status m2s_face_grad(const m2s_stencil *A, const double *u,
+                         const double *lam, double *gkx, double *gky,
+                         double *gkz, hipStream_t stream)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (A->kind != M2S_VAR7) return M2S_ERR_UNSUPPORTED;
+    if (A->dtype != M2S_F64) return M2S_ERR_DTYPE;
+    if (!u || !lam || !gkx || !gky || !gkz) return M2S_ERR_ARG;
+    Grid g{A->ext.nx, A->ext.ny, A->ext.nz};
+    return hip_status(launch_face_grad(g, u, lam, gkx, gky, gkz, stream));
+}
+
+m2s_status m2s_dot(const double *x, const double *y, int64_t n, double *out,
+                   hipStream_t stream)
+{
+    if (!x || !y || !out || n < 0) return M2S_ERR_ARG;
+    double *partials = nullptr;
+    // a private partials buffer per call keeps concurrent callers apart
+    if (hipMallocAsync((void **)&partials,
+                       sizeof(double) * dot_partials_capacity(),
+                       stream) != hipSuccess)
+        return M2S_ERR_HIP;
+    hipError_t e = hipMemsetAsync(partials, 0,
+                                  sizeof(double) * dot_partials_capacity(),
+                                  stream);
+    if (e == hipSuccess) e = launch_dot(x, y, n, partials, out, stream);
+    hipError_t f = hipFreeAsync(partials, stream);
+    return (e == hipSuccess && f == hipSuccess) ? M2S_OK : M2S_ERR_HIP;
+}
+
+m2s_status m2s_convert(const void *src, m2s_dtype src_t, void *dst,
+                       m2s_dtype dst_t, int64_t n, hipStream_t stream)
+{
+    if (!src || !dst || n < 0) return M2S_ERR_ARG;
+    if ((src_t != M2S_F64 && src_t != M2S_F32) ||
+        (dst_t != M2S_F64 && dst_t != M2S_F32))
+        return M2S_ERR_DTYPE;
+    return hip_status(launch_convert(src, src_t, dst, dst_t, n, stream));
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// Multigrid hierarchy and V-cycle.
+// ------------------------------------------------------------------------
+struct MgLevel {
+    m2s_stencil A;        // this level's operator (dtype = hierarchy prec)
+    void *kx = nullptr, *ky = nullptr, *kz = nullptr;  // owned (VAR7)
+    void *r = nullptr;    // level right-hand side (levels >= 1)
+    void *z = nullptr;    // level correction (levels >= 1)
+    m2s_workspace *ws = nullptr;
+};
+
+struct m2s_mg {
+    int levels;
+    m2s_dtype prec;
+    std::vector<MgLevel> L;
+    void *r0 = nullptr, *z0 = nullptr;  // level-0 float buffers (F32 prec)
+};
+
+namespace {
+
+// z_l = V-cycle(r_l) on level l.
+m2s_status vcycle_level(m2s_mg *mg, int l, const void *r, void *z,
+                        hipStream_t s)
+{
+    MgLevel &lv = mg->L[l];
+    m2s_status st;
+    // z = 0 followed by one SymGS: the forward half starts from zero
+    if ((st = half_sweep(lv.A, nullptr, 1.0, r, nullptr, lv.ws->scratch,
+                         false, true, lv.ws, s)) != M2S_OK)
+        return st;
+    if ((st = half_sweep(lv.A, nullptr, 1.0, r, lv.ws->scratch, z, true,
+                         false, lv.ws, s)) != M2S_OK)
+        return st;
+    if (l == mg->levels - 1) return M2S_OK;
+    MgLevel &cv = mg->L[l + 1];
+    M2S_TRY(launch_restrict(lv.A, r, z, cv.r, s));
+    if ((st = vcycle_level(mg, l + 1, cv.r, cv.z, s)) != M2S_OK) return st;
+    M2S_TRY(launch_prolong(lv.A, cv.z, z, s));
+    if ((st = half_sweep(lv.A, nullptr, 1.0, r, z, lv.ws->scratch, false,
+                         false, lv.ws, s)) != M2S_OK)
+        return st;
+    return half_sweep(lv.A, nullptr, 1.0, r, lv.ws->scratch, z, true, false,
+                      lv.ws, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+void m2s_mg_destroy(m2s_mg *mg)
+{
+    if (!mg) return;
+    (void)hipDeviceSynchronize();
+    for (auto &lv : mg->L) {
+        if (lv.kx) (void)hipFree(lv.kx);
+        if (lv.ky) (void)hipFree(lv.ky);
+        if (lv.kz) (void)hipFree(lv.kz);
+        if (lv.r) (void)hipFree(lv.r);
+        if (lv.z) (void)hipFree(lv.z);
+        m2s_workspace_destroy(lv.ws);
+    }
+    if (mg->r0) (void)hipFree(mg->r0);
+    if (mg->z0) (void)hipFree(mg->z0);
+    delete mg;
+}
+
+m2s_status m2s_mg_create(const m2s_stencil *fine, int levels, m2s_dtype prec,
+                         m2s_mg **out)
+{
+    m2s_status st = validate(fine);
+    if (st != M2S_OK) return st;
+    if (!out) return M2S_ERR_ARG;
+    *out = nullptr;
+    if (fine->kind == M2S_BLOCK7_5) return M2S_ERR_UNSUPPORTED;
+    if (fine->dtype != M2S_F64) return M2S_ERR_DTYPE;
+    if (prec != M2S_F64 && prec != M2S_F32) return M2S_ERR_DTYPE;
+    if (levels < 1 || levels > 12) return M2S_ERR_ARG;
+    const int f = 1 << (levels - 1);
+    if (fine->ext.nx % f || fine->ext.ny % f || fine->ext.nz % f)
+        return M2S_ERR_SHAPE;
+    m2s_mg *mg = new (std::nothrow) m2s_mg();
+    if (!mg) return M2S_ERR_HIP;
+    mg->levels = levels;
+    mg->prec = prec;
+    mg->L.resize(levels);
+    const size_t es = prec == M2S_F64 ? 8 : 4;
+    hipStream_t s = 0;
+    for (int l = 0; l < levels; ++l) {
+        MgLevel &lv = mg->L[l];
+        lv.A = *fine;
+        lv.A.dtype = prec;
+        lv.A.ext = m2s_extent{fine->ext.nx >> l, fine->ext.ny >> l,
+                              fine->ext.nz >> l};
+        const int64_t n = npoints(lv.A);
+        bool ok = true;
+        if (fine->kind == M2S_VAR7) {
+            Faces F{lv.A.ext.nx, lv.A.ext.ny, lv.A.ext.nz};
+            ok = hipMalloc(&lv.kx, es * F.nfx()) == hipSuccess &&
+                 hipMalloc(&lv.ky, es * F.nfy()) == hipSuccess &&
+                 hipMalloc(&lv.kz, es * F.nfz()) == hipSuccess;
+            if (ok && l == 0) {
+                Faces F0{fine->ext.nx, fine->ext.ny, fine->ext.nz};
+                ok = launch_convert(fine->kx, M2S_F64, lv.kx, prec, F0.nfx(),
+                                    s) == hipSuccess &&
+                     launch_convert(fine->ky, M2S_F64, lv.ky, prec, F0.nfy(),
+                                    s) == hipSuccess &&
+                     launch_convert(fine->kz, M2S_F64, lv.kz, prec, F0.nfz(),
+                                    s) == hipSuccess;
+            } else if (ok) {
+                MgLevel &pv = mg->L[l - 1];
+                Grid gf{pv.A.ext.nx, pv.A.ext.ny, pv.A.ext.nz};
+                ok = launch_var7_coarsen(prec, gf, pv.kx, pv.ky, pv.kz, lv.kx,
+                                         lv.ky, lv.kz, s) == hipSuccess;
+            }
+            lv.A.kx = lv.kx;
+            lv.A.ky = lv.ky;
+            lv.A.kz = lv.kz;
+        }
+        if (ok && l > 0)
+            ok = hipMalloc(&lv.r, es * n) == hipSuccess &&
+                 hipMalloc(&lv.z, es * n) == hipSuccess;
+        if (ok) ok = m2s_workspace_create(&lv.A, &lv.ws) == M2S_OK;
+        if (!ok) {
+            m2s_mg_destroy(mg);
+            return M2S_ERR_HIP;
+        }
+    }
+    if (prec == M2S_F32) {
+        const int64_t n = npoints(*fine);
+        if (hipMalloc(&mg->r0, 4 * n) != hipSuccess ||
+            hipMalloc(&mg->z0, 4 * n) != hipSuccess) {
+            m2s_mg_destroy(mg);
+            return M2S_ERR_HIP;
+        }
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {
+        m2s_mg_destroy(mg);
+        return M2S_ERR_HIP;
+    }
+    *out = mg;
+    return M2S_OK;
+}
+
+m2s_status m2s_mg_vcycle(m2s_mg *mg, const double *r, double *z,
+                         hipStream_t stream)
+{
+    if (!mg || !r || !z) return M2S_ERR_ARG;
+    const int64_t n = npoints(mg->L[0].A);
+    if (overlap(r, z, 8 * (size_t)n)) return M2S_ERR_ALIAS;
+    if (mg->prec == M2S_F64) return vcycle_level(mg, 0, r, z, stream);
+    M2S_TRY(launch_convert(r, M2S_F64, mg->r0, M2S_F32, n, stream));
+    m2s_status st = vcycle_level(mg, 0, mg->r0, mg->z0, stream);
+    if (st != M2S_OK) return st;
+    return hip_status(launch_convert(mg->z0, M2S_F32, z, M2S_F64, n, stream));
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// PCG.
+// ------------------------------------------------------------------------
+namespace {
+
+struct PcgBuffers {
+    double *r = nullptr, *z = nullptr, *p = nullptr, *ap = nullptr;
+    double *sc = nullptr, *partials = nullptr;
+    m2s_workspace *ws = nullptr;
+    ~PcgBuffers()
+    {
+        (void)hipDeviceSynchronize();
+        if (r) (void)hipFree(r);
+        if (z) (void)hipFree(z);
+        if (p) (void)hipFree(p);
+        if (ap) (void)hipFree(ap);
+        if (sc) (void)hipFree(sc);
+        if (partials) (void)hipFree(partials);
+        if (ws) m2s_workspace_destroy(ws);
+    }
+};
+
+m2s_status workspace_error(m2s_workspace *ws)
+{
+    if (!ws) return M2S_OK;
+    int e = 0;
+    if (hipMemcpy(&e, ws->err, sizeof(int), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return M2S_ERR_HIP;
+    if (e) {
+        uint64_t tk = 0;
+        (void)hipMemcpy(&tk, ws->ticket, sizeof(tk), hipMemcpyDeviceToHost);
+        (void)hipMemset(ws->err, 0, sizeof(int));
+        ws->ticket_base = tk;
+        return M2S_ERR_TIMEOUT;
+    }
+    return M2S_OK;
+}
+
+m2s_status mg_error(m2s_mg *mg)
+{
+    if (!mg) return M2S_OK;
+    for (auto &lv : mg->L) {
+        m2s_status st = workspace_error(lv.ws);
+        if (st != M2S_OK) return st;
+    }
+    return M2S_OK;
+}
+
+}  // namespace
+
+extern "C" m2s_status m2s_pcg_solve(const m2s_stencil *A,
+                                    m2s_precond precond, m2s_mg *mg,
+                                    const double *b, double *x,
+                                    const m2s_pcg_opts *opts,
+                                    m2s_pcg_info *info, double *hist,
+                                    hipStream_t stream)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (A->kind == M2S_BLOCK7_5) return M2S_ERR_UNSUPPORTED;
+    if (A->dtype != M2S_F64) return M2S_ERR_DTYPE;
+    if (!b || !x || !opts) return M2S_ERR_ARG;
+    if (opts->max_iter < 0) return M2S_ERR_ARG;
+    if (precond != M2S_PC_NONE && precond != M2S_PC_SYMGS &&
+        precond != M2S_PC_MG)
+        return M2S_ERR_ARG;
+    if (precond == M2S_PC_MG) {
+        if (!mg) return M2S_ERR_ARG;
+        const m2s_extent &e = mg->L[0].A.ext;
+        if (e.nx != A->ext.nx || e.ny != A->ext.ny || e.nz != A->ext.nz ||
+            mg->L[0].A.kind != A->kind)
+            return M2S_ERR_SHAPE;
+    }
+    const int64_t n = npoints(*A);
+    const size_t vb = 8 * (size_t)n;
+    if (overlap(b, x, vb)) return M2S_ERR_ALIAS;
+    PcgBuffers B;
+    if (hipMalloc((void **)&B.r, vb) != hipSuccess ||
+        hipMalloc((void **)&B.z, vb) != hipSuccess ||
+        hipMalloc((void **)&B.p, vb) != hipSuccess ||
+        hipMalloc((void **)&B.ap, vb) != hipSuccess ||
+        hipMalloc((void **)&B.sc, sizeof(double) * SC_N) != hipSuccess ||
+        hipMalloc((void **)&B.partials,
+                  sizeof(double) * dot_partials_capacity()) != hipSuccess)
+        return M2S_ERR_HIP;
+    M2S_TRY(hipMemsetAsync(B.sc, 0, sizeof(double) * SC_N, stream));
+    M2S_TRY(hipMemsetAsync(B.partials, 0,
+                           sizeof(double) * dot_partials_capacity(), stream));
+    if (precond == M2S_PC_SYMGS &&
+        (st = m2s_workspace_create(A, &B.ws)) != M2S_OK)
+        return st;
+    double hsc[SC_N];
+    auto fetch = [&]() -> m2s_status {
+        if (hipMemcpyAsync(hsc, B.sc, sizeof(hsc), hipMemcpyDeviceToHost,
+                           stream) != hipSuccess)
+            return M2S_ERR_HIP;
+        if (hipStreamSynchronize(stream) != hipSuccess) return M2S_ERR_HIP;
+        return M2S_OK;
+    };
+    auto true_residual = [&]() -> m2s_status {
+        M2S_TRY(launch_spmv(*A, x, B.ap, stream));
+        M2S_TRY(launch_residual(b, B.ap, B.r, n, B.partials, B.sc + SC_RR,
+                                stream));
+        return M2S_OK;
+    };
+    if ((st = true_residual()) != M2S_OK) return st;
+    if ((st = fetch()) != M2S_OK) return st;
+    const double normr0 = std::sqrt(hsc[SC_RR]);
+    double normr = normr0;
+    m2s_status result = M2S_ERR_NOT_CONVERGED;
+    int it = 0;
+    if (hist) hist[0] = 1.0;
+    if (!std::isfinite(normr0)) result = M2S_ERR_BREAKDOWN;
+    else if (normr0 == 0.0) result = M2S_OK;
+    else {
+        for (it = 1; it <= opts->max_iter; ++it) {
+            const double *zz = B.z;
+            if (precond == M2S_PC_NONE) {
+                zz = B.r;
+            } else if (precond == M2S_PC_SYMGS) {
+                if ((st = half_sweep(*A, nullptr, 1.0, B.r, nullptr,
+                                     B.ws->scratch, false, true, B.ws,
+                                     stream)) != M2S_OK)
+                    return st;
+                if ((st = half_sweep(*A, nullptr, 1.0, B.r, B.ws->scratch,
+                                     B.z, true, false, B.ws, stream)) !=
+                    M2S_OK)
+                    return st;
+            } else {
+                if ((st = m2s_mg_vcycle(mg, B.r, B.z, stream)) != M2S_OK)
+                    return st;
+            }
+            M2S_TRY(hipMemcpyAsync(B.sc + SC_RZ_OLD, B.sc + SC_RZ,
+                                   sizeof(double), hipMemcpyDeviceToDevice,
+                                   stream));
+            M2S_TRY(launch_dot(B.r, zz, n, B.partials, B.sc + SC_RZ, stream));
+            M2S_TRY(launch_update_p(zz, B.p, n, B.sc, it == 1, stream));
+            M2S_TRY(launch_spmv_dot(*A, B.p, B.ap, B.partials, B.sc + SC_PAP,
+                                    stream));
+            M2S_TRY(launch_update_xr(x, B.r, B.p, B.ap, n, B.sc, B.partials,
+                                     stream));
+            if ((st = fetch()) != M2S_OK) return st;
+            const double pap = hsc[SC_PAP];
+            normr = std::sqrt(hsc[SC_RR]);
+            if (!(pap > 0.0) || !std::isfinite(pap) || !std::isfinite(normr) ||
+                !std::isfinite(hsc[SC_RZ])) {
+                result = M2S_ERR_BREAKDOWN;
+                break;
+            }
+            const bool replace =
+                opts->replace_every > 0 && it % opts->replace_every == 0;
+            const bool check = opts->rtol > 0 && normr / normr0 <= opts->rtol;
+            if (replace || check) {
+                if ((st = true_residual()) != M2S_OK) return st;
+                if ((st = fetch()) != M2S_OK) return st;
+                normr = std::sqrt(hsc[SC_RR]);
+            }
+            if (hist) hist[it] = normr / normr0;
+            if (opts->rtol > 0 && normr / normr0 <= opts->rtol) {
+                result = M2S_OK;
+                break;
+            }
+        }
+        if (it > opts->max_iter) {
+            it = opts->max_iter;
+            if (opts->rtol <= 0) result = M2S_OK;
+        }
+    }
+    if (hipStreamSynchronize(stream) != hipSuccess) return M2S_ERR_HIP;
+    m2s_status werr = precond == M2S_PC_MG ? mg_error(mg)
+                                           : workspace_error(B.ws);
+    if (werr != M2S_OK) result = werr;
+    auto t1 = std::chrono::steady_clock::now();
+    if (info) {
+        // true residual of the returned x
+        if (true_residual() == M2S_OK && fetch() == M2S_OK)
+            info->true_rel_res =
+                normr0 > 0 ? std::sqrt(hsc[SC_RR]) / normr0 : 0.0;
+        info->iters = it;
+        info->rel_res = normr0 > 0 ? normr / normr0 : 0.0;
+        info->r0_norm = normr0;
+        info->status = result;
+        info->seconds = std::chrono::duration<double>(t1 - t0).count();
+    }
+    return result;
+}

@@ -1,0 +1,831 @@
+// k_ops.hip -- the Jacobi-style (embarrassingly parallel) stencil kernels
+// around the sweeps: SpMV for the three operators (Sec. 4.3.1), the strict
+// triangle parts, fused residual + injection restriction and injection
+// prolongation of the multigrid cycle (the "HPCG Prolong" matrix, Table 1),
+// VAR7 coarse-face construction, the face-coefficient gradient, and small
+// elementwise helpers.  All are HBM-bound; loads are coalesced along x.
+#include "m2s_internal.hpp"
+
+namespace m2s {
+
+// --------------------------------------------------------------------------
+// CONST27 SpMV: a 64x4 (x,y) tile per workgroup marches along z over a
+// chunk of planes.  Each plane (tile + 1-point halo) is staged in LDS with
+// coalesced loads; a thread keeps the 3x3 plane sums of the planes below,
+// at and above its point in registers, so every x value is read from HBM
+// once per chunk and 9 times from LDS.
+//   y = diag * x + off * ((S9(k-1) + S8(k)) + S9(k+1))
+// S9 = 3x3 sum in a plane, S8 = the same without the centre.
+// --------------------------------------------------------------------------
+constexpr int SP_TX = 64, SP_TY = 4, SP_KCHUNK = 16;
+
+template <typename T>
+__device__ __forceinline__ void sp27_stage(T (*tile)[SP_TX + 2], const T *x,
+                                           const Grid &g, int i0, int j0,
+                                           int k)
+{
+    const int tid = threadIdx.y * SP_TX + threadIdx.x;
+    constexpr int W = SP_TX + 2, H = SP_TY + 2;
+    for (int e = tid; e < W * H; e += SP_TX * SP_TY) {
+        const int ty = e / W, tx = e - (e / W) * W;
+        const int i = i0 + tx - 1, j = j0 + ty - 1;
+        T v = T(0);
+        if (k >= 0 && k < g.nz && i >= 0 && i < g.nx && j >= 0 && j < g.ny)
+            v = x[g.idx(i, j, k)];
+        tile[ty][tx] = v;
+    }
+}
+
+template <typename T, bool DOT>
+__global__ void __launch_bounds__(SP_TX *SP_TY)
+    spmv27_kernel(Grid g, T diag, T off, const T *__restrict__ x,
+                  T *__restrict__ y, double *partials, double *dot_out,
+                  unsigned *counter);
+
+template <typename T>
+struct Plane9 {
+    T s9, s8, c;
+};
+
+template <typename T>
+__device__ __forceinline__ Plane9<T> sp27_sums(T (*tile)[SP_TX + 2])
+{
+    const int tx = threadIdx.x + 1, ty = threadIdx.y + 1;
+    T a = (tile[ty - 1][tx - 1] + tile[ty - 1][tx]) + tile[ty - 1][tx + 1];
+    T b = tile[ty][tx - 1] + tile[ty][tx + 1];
+    T c = (tile[ty + 1][tx - 1] + tile[ty + 1][tx]) + tile[ty + 1][tx + 1];
+    Plane9<T> p;
+    p.c = tile[ty][tx];
+    p.s8 = (a + b) + c;
+    p.s9 = (a + (b + p.c)) + c;
+    return p;
+}
+
+// Deterministic block reduction of one double per thread into partials[b];
+// the last block to finish sums the partials in index order into *out and
+// re-arms the counter.
+__device__ void block_reduce_finish(double v, double *partials, double *out,
+                                    unsigned *counter)
+{
+    __shared__ double red[1024];
+    __shared__ bool last;
+    const int nt = blockDim.x * blockDim.y * blockDim.z;
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y +
+                                                blockDim.y * threadIdx.z);
+    const int nb = gridDim.x * gridDim.y * gridDim.z;
+    const int bid = blockIdx.x + gridDim.x * (blockIdx.y +
+                                              gridDim.y * blockIdx.z);
+    red[tid] = v;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (s < nt && tid < s && tid + s < nt) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        partials[bid] = red[0];
+        __threadfence();
+        unsigned prev = atomicAdd(counter, 1u);
+        last = (prev == (unsigned)nb - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double acc = 0.0;
+    for (int b = tid; b < nb; b += nt)
+        acc += __hip_atomic_load(partials + b, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+    red[tid] = acc;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (s < nt && tid < s && tid + s < nt) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        *out = red[0];
+        *counter = 0u;
+    }
+}
+
+template <typename T, bool DOT>
+__global__ void __launch_bounds__(SP_TX *SP_TY)
+    spmv27_kernel(Grid g, T diag, T off, const T *__restrict__ x,
+                  T *__restrict__ y, double *partials, double *dot_out,
+                  unsigned *counter)
+{
+    __shared__ T tile[2][SP_TY + 2][SP_TX + 2];
+    const int i0 = blockIdx.x * SP_TX, j0 = blockIdx.y * SP_TY;
+    const int k0 = blockIdx.z * SP_KCHUNK;
+    const int k1 = min(g.nz, k0 + SP_KCHUNK);
+    const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
+    const bool act = i < g.nx && j < g.ny;
+    sp27_stage(tile[0], x, g, i0, j0, k0 - 1);
+    sp27_stage(tile[1], x, g, i0, j0, k0);
+    __syncthreads();
+    Plane9<T> pm = sp27_sums(tile[0]);
+    Plane9<T> p0 = sp27_sums(tile[1]);
+    double acc = 0.0;
+    int buf = 0;
+    for (int k = k0; k < k1; ++k) {
+        __syncthreads();
+        sp27_stage(tile[buf], x, g, i0, j0, k + 1);
+        __syncthreads();
+        Plane9<T> pp = sp27_sums(tile[buf]);
+        buf ^= 1;
+        if (act) {
+            T nb = (pm.s9 + p0.s8) + pp.s9;
+            T v = fma(off, nb, diag * p0.c);
+            y[g.idx(i, j, k)] = v;
+            if (DOT) acc = fma((double)p0.c, (double)v, acc);
+        }
+        pm = p0;
+        p0 = pp;
+    }
+    if (DOT) block_reduce_finish(acc, partials, dot_out, counter);
+}
+
+// --------------------------------------------------------------------------
+// VAR7 SpMV (optionally fused with x.y).
+// --------------------------------------------------------------------------
+template <typename T, bool DOT>
+__global__ void __launch_bounds__(256)
+    spmv_var7_kernel(Grid g, const T *__restrict__ kx,
+                     const T *__restrict__ ky, const T *__restrict__ kz,
+                     const T *__restrict__ x, T *__restrict__ y,
+                     double *partials, double *dot_out, unsigned *counter)
+{
+    Faces F{g.nx, g.ny, g.nz};
+    double acc = 0.0;
+    const int64_t n = g.size();
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(p % g.nx);
+        const int64_t t = p / g.nx;
+        const int j = (int)(t % g.ny), k = (int)(t / g.ny);
+        const T kxm = kx[F.ix(i, j, k)], kxp = kx[F.ix(i + 1, j, k)];
+        const T kym = ky[F.iy(i, j, k)], kyp = ky[F.iy(i, j + 1, k)];
+        const T kzm = kz[F.iz(i, j, k)], kzp = kz[F.iz(i, j, k + 1)];
+        const T xc = x[p];
+        const T vmx = i > 0 ? x[p - 1] : T(0);
+        const T vpx = i < g.nx - 1 ? x[p + 1] : T(0);
+        const T vmy = j > 0 ? x[p - g.nx] : T(0);
+        const T vpy = j < g.ny - 1 ? x[p + g.nx] : T(0);
+        const int64_t pl = (int64_t)g.nx * g.ny;
+        const T vmz = k > 0 ? x[p - pl] : T(0);
+        const T vpz = k < g.nz - 1 ? x[p + pl] : T(0);
+        T d = ((kxm + kxp) + (kym + kyp)) + (kzm + kzp);
+        T s1 = fma(kxm, vmx, kxp * vpx);
+        T s2 = fma(kym, vmy, kyp * vpy);
+        T s3 = fma(kzm, vmz, kzp * vpz);
+        T v = fma(d, xc, -((s1 + s2) + s3));
+        y[p] = v;
+        if (DOT) acc = fma((double)xc, (double)v, acc);
+    }
+    if (DOT) block_reduce_finish(acc, partials, dot_out, counter);
+}
+
+// --------------------------------------------------------------------------
+// BLOCK7 SpMV.
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+    spmv_block7_kernel(Grid g, Block7Consts C, const double *__restrict__ x,
+                       double *__restrict__ y)
+{
+    const int64_t n = g.size();
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(p % g.nx);
+        const int64_t t = p / g.nx;
+        const int j = (int)(t % g.ny), k = (int)(t / g.ny);
+        const int di[7] = {0, -1, 1, 0, 0, 0, 0};
+        const int dj[7] = {0, 0, 0, -1, 1, 0, 0};
+        const int dk[7] = {0, 0, 0, 0, 0, -1, 1};
+        double s[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < 7; ++d) {
+            const int ii = i + di[d], jj = j + dj[d], kk = k + dk[d];
+            if (!g.in(ii, jj, kk)) continue;
+            const int64_t q = 5 * g.idx(ii, jj, kk);
+            double xq[5];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) xq[c] = x[q + c];
+#pragma unroll
+            for (int a = 0; a < 5; ++a)
+#pragma unroll
+                for (int c = 0; c < 5; ++c)
+                    s[a] = fma(C.B[d][5 * a + c], xq[c], s[a]);
+        }
+#pragma unroll
+        for (int a = 0; a < 5; ++a) y[5 * p + a] = s[a];
+    }
+}
+
+// --------------------------------------------------------------------------
+// Strict lower / upper triangle parts (CONST27, VAR7).
+// --------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+    spmv_part_kernel(Grid g, int kind, int part, T off, const T *kx,
+                     const T *ky, const T *kz, const T *__restrict__ x,
+                     T *__restrict__ y)
+{
+    Faces F{g.nx, g.ny, g.nz};
+    const int64_t n = g.size();
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(p % g.nx);
+        const int64_t t = p / g.nx;
+        const int j = (int)(t % g.ny), k = (int)(t / g.ny);
+        T s = T(0);
+        if (kind == M2S_CONST27) {
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        const int o = (dz * 3 + dy) * 3 + dx;
+                        if (o == 0 || (part < 0) != (o < 0)) continue;
+                        if (!g.in(i + dx, j + dy, k + dz)) continue;
+                        s += x[g.idx(i + dx, j + dy, k + dz)];
+                    }
+            s = off * s;
+        } else {
+            if (part < 0) {
+                T a = k > 0 ? kz[F.iz(i, j, k)] * x[g.idx(i, j, k - 1)] : T(0);
+                T b = j > 0 ? ky[F.iy(i, j, k)] * x[g.idx(i, j - 1, k)] : T(0);
+                T c = i > 0 ? kx[F.ix(i, j, k)] * x[g.idx(i - 1, j, k)] : T(0);
+                s = -((a + b) + c);
+            } else {
+                T a = i < g.nx - 1 ? kx[F.ix(i + 1, j, k)] *
+                                         x[g.idx(i + 1, j, k)]
+                                   : T(0);
+                T b = j < g.ny - 1 ? ky[F.iy(i, j + 1, k)] *
+                                         x[g.idx(i, j + 1, k)]
+                                   : T(0);
+                T c = k < g.nz - 1 ? kz[F.iz(i, j, k + 1)] *
+                                         x[g.idx(i, j, k + 1)]
+                                   : T(0);
+                s = -((a + b) + c);
+            }
+        }
+        y[p] = s;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Fused residual + injection restriction: rc[I,J,K] = r - A z at the fine
+// point (2I, 2J, 2K).
+// --------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+    restrict_kernel(Grid gf, int kind, T diag, T off, const T *kx,
+                    const T *ky, const T *kz, const T *__restrict__ r,
+                    const T *__restrict__ z, T *__restrict__ rc)
+{
+    const Grid gc{gf.nx / 2, gf.ny / 2, gf.nz / 2};
+    Faces F{gf.nx, gf.ny, gf.nz};
+    const int64_t n = gc.size();
+    for (int64_t pc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pc < n;
+         pc += (int64_t)gridDim.x * blockDim.x) {
+        const int I = (int)(pc % gc.nx);
+        const int64_t t = pc / gc.nx;
+        const int J = (int)(t % gc.ny), K = (int)(t / gc.ny);
+        const int i = 2 * I, j = 2 * J, k = 2 * K;
+        const int64_t p = gf.idx(i, j, k);
+        T az;
+        if (kind == M2S_CONST27) {
+            T s = T(0);
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy) {
+                    T row = T(0);
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        if ((dx | dy | dz) == 0) continue;
+                        if (!gf.in(i + dx, j + dy, k + dz)) continue;
+                        row += z[gf.idx(i + dx, j + dy, k + dz)];
+                    }
+                    s += row;
+                }
+            az = fma(off, s, diag * z[p]);
+        } else {
+            const T kxm = kx[F.ix(i, j, k)], kxp = kx[F.ix(i + 1, j, k)];
+            const T kym = ky[F.iy(i, j, k)], kyp = ky[F.iy(i, j + 1, k)];
+            const T kzm = kz[F.iz(i, j, k)], kzp = kz[F.iz(i, j, k + 1)];
+            const T vmx = i > 0 ? z[p - 1] : T(0);
+            const T vpx = i < gf.nx - 1 ? z[p + 1] : T(0);
+            const T vmy = j > 0 ? z[p - gf.nx] : T(0);
+            const T vpy = j < gf.ny - 1 ? z[p + gf.nx] : T(0);
+            const int64_t pl = (int64_t)gf.nx * gf.ny;
+            const T vmz = k > 0 ? z[p - pl] : T(0);
+            const T vpz = k < gf.nz - 1 ? z[p + pl] : T(0);
+            T d = ((kxm + kxp) + (kym + kyp)) + (kzm + kzp);
+            T s1 = fma(kxm, vmx, kxp * vpx);
+            T s2 = fma(kym, vmy, kyp * vpy);
+            T s3 = fma(kzm, vmz, kzp * vpz);
+            az = fma(d, z[p], -((s1 + s2) + s3));
+        }
+        rc[pc] = r[p] - az;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    prolong_kernel(Grid gf, const T *__restrict__ zc, T *__restrict__ z)
+{
+    const Grid gc{gf.nx / 2, gf.ny / 2, gf.nz / 2};
+    const int64_t n = gc.size();
+    for (int64_t pc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pc < n;
+         pc += (int64_t)gridDim.x * blockDim.x) {
+        const int I = (int)(pc % gc.nx);
+        const int64_t t = pc / gc.nx;
+        const int J = (int)(t % gc.ny), K = (int)(t / gc.ny);
+        const int64_t p = gf.idx(2 * I, 2 * J, 2 * K);
+        z[p] += zc[pc];
+    }
+}
+
+// Coarse VAR7 faces: interior coarse face I spans fine faces 2I-1 and 2I,
+// combined in series, over doubled spacing: ab / (2 (a + b)); the first
+// face on an axis covers fine face 0 only (value / 4); transverse position
+// on the coincident fine row.
+template <typename T>
+__device__ __forceinline__ T hm4(T a, T b)
+{
+    return (a * b) / (T(2) * (a + b));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    coarsen_kernel(Grid gf, const T *kx, const T *ky, const T *kz, T *kxc,
+                   T *kyc, T *kzc)
+{
+    const Grid gc{gf.nx / 2, gf.ny / 2, gf.nz / 2};
+    Faces Ff{gf.nx, gf.ny, gf.nz}, Fc{gc.nx, gc.ny, gc.nz};
+    const int64_t nx = Fc.nfx(), ny = Fc.nfy(), nz = Fc.nfz();
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+         e < nx + ny + nz; e += (int64_t)gridDim.x * blockDim.x) {
+        if (e < nx) {
+            const int I = (int)(e % (gc.nx + 1));
+            const int64_t t = e / (gc.nx + 1);
+            const int J = (int)(t % gc.ny), K = (int)(t / gc.ny);
+            kxc[e] = I == 0 ? kx[Ff.ix(0, 2 * J, 2 * K)] / T(4)
+                            : hm4(kx[Ff.ix(2 * I - 1, 2 * J, 2 * K)],
+                                  kx[Ff.ix(2 * I, 2 * J, 2 * K)]);
+        } else if (e < nx + ny) {
+            const int64_t f = e - nx;
+            const int I = (int)(f % gc.nx);
+            const int64_t t = f / gc.nx;
+            const int J = (int)(t % (gc.ny + 1)), K = (int)(t / (gc.ny + 1));
+            kyc[f] = J == 0 ? ky[Ff.iy(2 * I, 0, 2 * K)] / T(4)
+                            : hm4(ky[Ff.iy(2 * I, 2 * J - 1, 2 * K)],
+                                  ky[Ff.iy(2 * I, 2 * J, 2 * K)]);
+        } else {
+            const int64_t f = e - nx - ny;
+            const int I = (int)(f % gc.nx);
+            const int64_t t = f / gc.nx;
+            const int J = (int)(t % gc.ny), K = (int)(t / gc.ny);
+            kzc[f] = K == 0 ? kz[Ff.iz(2 * I, 2 * J, 0)] / T(4)
+                            : hm4(kz[Ff.iz(2 * I, 2 * J, 2 * K - 1)],
+                                  kz[Ff.iz(2 * I, 2 * J, 2 * K)]);
+        }
+    }
+}
+
+// dL/dk_f = -(lam_p - lam_q)(u_p - u_q), zero ghosts.
+__global__ void __launch_bounds__(256)
+    face_grad_kernel(Grid g, const double *__restrict__ u,
+                     const double *__restrict__ lam, double *gx, double *gy,
+                     double *gz)
+{
+    Faces F{g.nx, g.ny, g.nz};
+    const int64_t nfx = F.nfx(), nfy = F.nfy(), nfz = F.nfz();
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+         e < nfx + nfy + nfz; e += (int64_t)gridDim.x * blockDim.x) {
+        int i, j, k, dx = 0, dy = 0, dz = 0;
+        double *out;
+        int64_t f;
+        if (e < nfx) {
+            f = e;
+            i = (int)(f % (g.nx + 1));
+            const int64_t t = f / (g.nx + 1);
+            j = (int)(t % g.ny);
+            k = (int)(t / g.ny);
+            dx = 1;
+            out = gx;
+        } else if (e < nfx + nfy) {
+            f = e - nfx;
+            i = (int)(f % g.nx);
+            const int64_t t = f / g.nx;
+            j = (int)(t % (g.ny + 1));
+            k = (int)(t / (g.ny + 1));
+            dy = 1;
+            out = gy;
+        } else {
+            f = e - nfx - nfy;
+            i = (int)(f % g.nx);
+            const int64_t t = f / g.nx;
+            j = (int)(t % g.ny);
+            k = (int)(t / g.ny);
+            dz = 1;
+            out = gz;
+        }
+        // face between a = (i,j,k) - d and b = (i,j,k)
+        const int ia = i - dx, ja = j - dy, ka = k - dz;
+        const bool ina = g.in(ia, ja, ka), inb = g.in(i, j, k);
+        const double ua = ina ? u[g.idx(ia, ja, ka)] : 0.0;
+        const double la = ina ? lam[g.idx(ia, ja, ka)] : 0.0;
+        const double ub = inb ? u[g.idx(i, j, k)] : 0.0;
+        const double lb = inb ? lam[g.idx(i, j, k)] : 0.0;
+        out[f] = -(lb - la) * (ub - ua);
+    }
+}
+
+template <typename S, typename D>
+__global__ void __launch_bounds__(256)
+    convert_kernel(const S *__restrict__ s, D *__restrict__ d, int64_t n)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x)
+        d[p] = (D)s[p];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) fill_kernel(T *d, int64_t n, T v)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x)
+        d[p] = v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) scale_kernel(T *d, int64_t n, T a)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x)
+        d[p] *= a;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    add_kernel(T *__restrict__ d, const T *__restrict__ s, int64_t n)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x)
+        d[p] += s[p];
+}
+
+__global__ void __launch_bounds__(256)
+    copy_kernel(const double4 *__restrict__ s, double4 *__restrict__ d,
+                int64_t n4, const char *__restrict__ stail,
+                char *__restrict__ dtail, int tail)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n4;
+         p += (int64_t)gridDim.x * blockDim.x)
+        d[p] = s[p];
+    if (blockIdx.x == 0 && (int)threadIdx.x < tail)
+        dtail[threadIdx.x] = stail[threadIdx.x];
+}
+
+// --------------------------------------------------------------------------
+// CG vector kernels (double) with deterministic reductions.
+// --------------------------------------------------------------------------
+constexpr int kRedBlocks = 1024;
+int dot_partials_capacity() { return kRedBlocks + 8; }
+
+// partials layout: [0, kRedBlocks) per-block values, then a counter word.
+static unsigned *counter_of(double *partials)
+{
+    return (unsigned *)(partials + kRedBlocks);
+}
+
+__global__ void __launch_bounds__(256)
+    dot_kernel(const double *__restrict__ x, const double *__restrict__ y,
+               int64_t n, double *partials, double *out, unsigned *counter)
+{
+    double acc = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x)
+        acc = fma(x[p], y[p], acc);
+    block_reduce_finish(acc, partials, out, counter);
+}
+
+__global__ void __launch_bounds__(256)
+    residual_kernel(const double *__restrict__ b, const double *__restrict__ ax,
+                    double *__restrict__ r, int64_t n, double *partials,
+                    double *out, unsigned *counter)
+{
+    double acc = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const double v = b[p] - ax[p];
+        r[p] = v;
+        acc = fma(v, v, acc);
+    }
+    block_reduce_finish(acc, partials, out, counter);
+}
+
+__global__ void __launch_bounds__(256)
+    update_p_kernel(const double *__restrict__ z, double *__restrict__ p,
+                    int64_t n, const double *sc, int first)
+{
+    const double beta = first ? 0.0 : sc[SC_RZ] / sc[SC_RZ_OLD];
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        p[q] = first ? z[q] : fma(beta, p[q], z[q]);
+}
+
+__global__ void __launch_bounds__(256)
+    update_xr_kernel(double *__restrict__ x, double *__restrict__ r,
+                     const double *__restrict__ p,
+                     const double *__restrict__ ap, int64_t n, double *sc,
+                     double *partials, unsigned *counter)
+{
+    const double alpha = sc[SC_RZ] / sc[SC_PAP];
+    double acc = 0.0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        x[q] = fma(alpha, p[q], x[q]);
+        const double v = fma(-alpha, ap[q], r[q]);
+        r[q] = v;
+        acc = fma(v, v, acc);
+    }
+    block_reduce_finish(acc, partials, sc + SC_RR, counter);
+}
+
+static int blocks_for(int64_t n, int threads = 256, int cap = 8192)
+{
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+// --------------------------------------------------------------------------
+// Host launchers.
+// --------------------------------------------------------------------------
+template <typename T, bool DOT>
+static hipError_t sp27(const m2s_stencil &A, const void *x, void *y,
+                       double *partials, double *out, hipStream_t s)
+{
+    Grid g{A.ext.nx, A.ext.ny, A.ext.nz};
+    dim3 block(SP_TX, SP_TY);
+    dim3 grid((g.nx + SP_TX - 1) / SP_TX, (g.ny + SP_TY - 1) / SP_TY,
+              (g.nz + SP_KCHUNK - 1) / SP_KCHUNK);
+    if (DOT && (int64_t)grid.x * grid.y * grid.z > kRedBlocks) {
+        // too many blocks for the partials buffer: plain SpMV then a dot
+        hipLaunchKernelGGL((spmv27_kernel<T, false>), grid, block, 0, s, g,
+                           (T)A.diag, (T)A.offdiag, (const T *)x, (T *)y,
+                           nullptr, nullptr, nullptr);
+        hipLaunchKernelGGL(dot_kernel, dim3(blocks_for(g.size(), 256,
+                                                       kRedBlocks)),
+                           dim3(256), 0, s, (const double *)x,
+                           (const double *)y, g.size(), partials, out,
+                           counter_of(partials));
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((spmv27_kernel<T, DOT>), grid, block, 0, s, g,
+                       (T)A.diag, (T)A.offdiag, (const T *)x, (T *)y,
+                       partials, out, DOT ? counter_of(partials) : nullptr);
+    return hipGetLastError();
+}
+
+template <typename T, bool DOT>
+static hipError_t spv7(const m2s_stencil &A, const void *x, void *y,
+                       double *partials, double *out, hipStream_t s)
+{
+    Grid g{A.ext.nx, A.ext.ny, A.ext.nz};
+    const int nb = blocks_for(g.size(), 256, DOT ? kRedBlocks : 8192);
+    hipLaunchKernelGGL((spmv_var7_kernel<T, DOT>), dim3(nb), dim3(256), 0, s,
+                       g, (const T *)A.kx, (const T *)A.ky, (const T *)A.kz,
+                       (const T *)x, (T *)y, partials, out,
+                       DOT ? counter_of(partials) : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t fill_block7_consts(const double *blocks_host, Block7Consts &C);
+
+hipError_t launch_spmv(const m2s_stencil &A, const void *x, void *y,
+                       hipStream_t s)
+{
+    switch (A.kind) {
+    case M2S_CONST27:
+        return A.dtype == M2S_F64
+                   ? sp27<double, false>(A, x, y, nullptr, nullptr, s)
+                   : sp27<float, false>(A, x, y, nullptr, nullptr, s);
+    case M2S_VAR7:
+        return A.dtype == M2S_F64
+                   ? spv7<double, false>(A, x, y, nullptr, nullptr, s)
+                   : spv7<float, false>(A, x, y, nullptr, nullptr, s);
+    case M2S_BLOCK7_5: {
+        Block7Consts C{};
+        hipError_t e = fill_block7_consts(A.blocks, C);
+        if (e != hipSuccess) return e;
+        Grid g{A.ext.nx, A.ext.ny, A.ext.nz};
+        hipLaunchKernelGGL(spmv_block7_kernel, dim3(blocks_for(g.size())),
+                           dim3(256), 0, s, g, C, (const double *)x,
+                           (double *)y);
+        return hipGetLastError();
+    }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_spmv_dot(const m2s_stencil &A, const double *p, double *ap,
+                           double *partials, double *out, hipStream_t s)
+{
+    if (A.kind == M2S_CONST27) return sp27<double, true>(A, p, ap, partials, out, s);
+    return spv7<double, true>(A, p, ap, partials, out, s);
+}
+
+hipError_t launch_spmv_part(const m2s_stencil &A, int part, const void *x,
+                            void *y, hipStream_t s)
+{
+    Grid g{A.ext.nx, A.ext.ny, A.ext.nz};
+    const int nb = blocks_for(g.size());
+    if (A.dtype == M2S_F64)
+        hipLaunchKernelGGL(spmv_part_kernel<double>, dim3(nb), dim3(256), 0,
+                           s, g, (int)A.kind, part, A.offdiag,
+                           (const double *)A.kx, (const double *)A.ky,
+                           (const double *)A.kz, (const double *)x,
+                           (double *)y);
+    else
+        hipLaunchKernelGGL(spmv_part_kernel<float>, dim3(nb), dim3(256), 0, s,
+                           g, (int)A.kind, part, (float)A.offdiag,
+                           (const float *)A.kx, (const float *)A.ky,
+                           (const float *)A.kz, (const float *)x,
+                           (float *)y);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict(const m2s_stencil &A, const void *r, const void *z,
+                           void *rc, hipStream_t s)
+{
+    Grid g{A.ext.nx, A.ext.ny, A.ext.nz};
+    const int nb = blocks_for(g.size() / 8 + 1);
+    if (A.dtype == M2S_F64)
+        hipLaunchKernelGGL(restrict_kernel<double>, dim3(nb), dim3(256), 0, s,
+                           g, (int)A.kind, A.diag, A.offdiag,
+                           (const double *)A.kx, (const double *)A.ky,
+                           (const double *)A.kz, (const double *)r,
+                           (const double *)z, (double *)rc);
+    else
+        hipLaunchKernelGGL(restrict_kernel<float>, dim3(nb), dim3(256), 0, s,
+                           g, (int)A.kind, (float)A.diag, (float)A.offdiag,
+                           (const float *)A.kx, (const float *)A.ky,
+                           (const float *)A.kz, (const float *)r,
+                           (const float *)z, (float *)rc);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong(const m2s_stencil &A, const void *zc, void *z,
+                          hipStream_t s)
+{
+    Grid g{A.ext.nx, A.ext.ny, A.ext.nz};
+    const int nb = blocks_for(g.size() / 8 + 1);
+    if (A.dtype == M2S_F64)
+        hipLaunchKernelGGL(prolong_kernel<double>, dim3(nb), dim3(256), 0, s,
+                           g, (const double *)zc, (double *)z);
+    else
+        hipLaunchKernelGGL(prolong_kernel<float>, dim3(nb), dim3(256), 0, s,
+                           g, (const float *)zc, (float *)z);
+    return hipGetLastError();
+}
+
+hipError_t launch_var7_coarsen(m2s_dtype t, Grid fine, const void *kx,
+                               const void *ky, const void *kz, void *kxc,
+                               void *kyc, void *kzc, hipStream_t s)
+{
+    const int nb = blocks_for(fine.size() / 2 + 64);
+    if (t == M2S_F64)
+        hipLaunchKernelGGL(coarsen_kernel<double>, dim3(nb), dim3(256), 0, s,
+                           fine, (const double *)kx, (const double *)ky,
+                           (const double *)kz, (double *)kxc, (double *)kyc,
+                           (double *)kzc);
+    else
+        hipLaunchKernelGGL(coarsen_kernel<float>, dim3(nb), dim3(256), 0, s,
+                           fine, (const float *)kx, (const float *)ky,
+                           (const float *)kz, (float *)kxc, (float *)kyc,
+                           (float *)kzc);
+    return hipGetLastError();
+}
+
+hipError_t launch_face_grad(Grid g, const double *u, const double *lam,
+                            double *gx, double *gy, double *gz, hipStream_t s)
+{
+    Faces F{g.nx, g.ny, g.nz};
+    const int nb = blocks_for(F.nfx() + F.nfy() + F.nfz());
+    hipLaunchKernelGGL(face_grad_kernel, dim3(nb), dim3(256), 0, s, g, u, lam,
+                       gx, gy, gz);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(const void *src, m2s_dtype st, void *dst,
+                          m2s_dtype dt, int64_t n, hipStream_t s)
+{
+    const int nb = blocks_for(n);
+    if (st == M2S_F64 && dt == M2S_F32)
+        hipLaunchKernelGGL((convert_kernel<double, float>), dim3(nb),
+                           dim3(256), 0, s, (const double *)src, (float *)dst,
+                           n);
+    else if (st == M2S_F32 && dt == M2S_F64)
+        hipLaunchKernelGGL((convert_kernel<float, double>), dim3(nb),
+                           dim3(256), 0, s, (const float *)src,
+                           (double *)dst, n);
+    else if (st == M2S_F64)
+        hipLaunchKernelGGL((convert_kernel<double, double>), dim3(nb),
+                           dim3(256), 0, s, (const double *)src,
+                           (double *)dst, n);
+    else
+        hipLaunchKernelGGL((convert_kernel<float, float>), dim3(nb),
+                           dim3(256), 0, s, (const float *)src, (float *)dst,
+                           n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(void *dst, m2s_dtype t, int64_t n, double v,
+                       hipStream_t s)
+{
+    const int nb = blocks_for(n);
+    if (t == M2S_F64)
+        hipLaunchKernelGGL(fill_kernel<double>, dim3(nb), dim3(256), 0, s,
+                           (double *)dst, n, v);
+    else
+        hipLaunchKernelGGL(fill_kernel<float>, dim3(nb), dim3(256), 0, s,
+                           (float *)dst, n, (float)v);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(void *x, m2s_dtype t, int64_t n, double a,
+                        hipStream_t s)
+{
+    const int nb = blocks_for(n);
+    if (t == M2S_F64)
+        hipLaunchKernelGGL(scale_kernel<double>, dim3(nb), dim3(256), 0, s,
+                           (double *)x, n, a);
+    else
+        hipLaunchKernelGGL(scale_kernel<float>, dim3(nb), dim3(256), 0, s,
+                           (float *)x, n, (float)a);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(void *x, const void *y, m2s_dtype t, int64_t n,
+                      hipStream_t s)
+{
+    const int nb = blocks_for(n);
+    if (t == M2S_F64)
+        hipLaunchKernelGGL(add_kernel<double>, dim3(nb), dim3(256), 0, s,
+                           (double *)x, (const double *)y, n);
+    else
+        hipLaunchKernelGGL(add_kernel<float>, dim3(nb), dim3(256), 0, s,
+                           (float *)x, (const float *)y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, int64_t bytes,
+                       hipStream_t s)
+{
+    if (((uintptr_t)dst | (uintptr_t)src) & 31)
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+    const int64_t n4 = bytes / 32;
+    const int tail = (int)(bytes - n4 * 32);
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks_for(n4 + 1)), dim3(256), 0, s,
+                       (const double4 *)src, (double4 *)dst, n4,
+                       (const char *)src + n4 * 32, (char *)dst + n4 * 32,
+                       tail);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(const double *x, const double *y, int64_t n,
+                      double *partials, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(dot_kernel, dim3(blocks_for(n, 256, kRedBlocks)),
+                       dim3(256), 0, s, x, y, n, partials, out,
+                       counter_of(partials));
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const double *b, const double *ax, double *r,
+                           int64_t n, double *partials, double *rr_out,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(residual_kernel, dim3(blocks_for(n, 256, kRedBlocks)),
+                       dim3(256), 0, s, b, ax, r, n, partials, rr_out,
+                       counter_of(partials));
+    return hipGetLastError();
+}
+
+hipError_t launch_update_p(const double *z, double *p, int64_t n,
+                           const double *sc, bool first, hipStream_t s)
+{
+    hipLaunchKernelGGL(update_p_kernel, dim3(blocks_for(n)), dim3(256), 0, s,
+                       z, p, n, sc, first ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_xr(double *x, double *r, const double *p,
+                            const double *ap, int64_t n, double *sc,
+                            double *partials, hipStream_t s)
+{
+    hipLaunchKernelGGL(update_xr_kernel, dim3(blocks_for(n, 256, kRedBlocks)),
+                       dim3(256), 0, s, x, r, p, ap, n, sc, partials,
+                       counter_of(partials));
+    return hipGetLastError();
+}
+
+}  // namespace m2s

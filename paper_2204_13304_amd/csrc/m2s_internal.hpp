@@ -1,0 +1,162 @@
+// m2s_internal.hpp -- types and device helpers shared by the HIP kernels and
+// the host side of libm2s.so.  Not part of the public ABI (include/m2s.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/m2s.h"
+
+namespace m2s {
+
+// Grid with x fastest: p = (k*ny + j)*nx + i.
+struct Grid {
+    int nx, ny, nz;
+    __host__ __device__ int64_t idx(int i, int j, int k) const
+    {
+        return ((int64_t)k * ny + j) * nx + i;
+    }
+    __host__ __device__ int64_t size() const { return (int64_t)nx * ny * nz; }
+    __host__ __device__ bool in(int i, int j, int k) const
+    {
+        return i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
+    }
+};
+
+// A backward sweep is a forward sweep in reflected ("virtual") coordinates
+// iv = nx-1-i, jv = ny-1-j, kv = nz-1-k.  Every kernel works in virtual
+// coordinates and maps to memory through this helper.
+template <bool BWD>
+struct Virt {
+    Grid g;
+    __device__ int64_t idx(int iv, int jv, int kv) const
+    {
+        return BWD ? g.idx(g.nx - 1 - iv, g.ny - 1 - jv, g.nz - 1 - kv)
+                   : g.idx(iv, jv, kv);
+    }
+    __device__ int ri(int iv) const { return BWD ? g.nx - 1 - iv : iv; }
+    __device__ int rj(int jv) const { return BWD ? g.ny - 1 - jv : jv; }
+    __device__ int rk(int kv) const { return BWD ? g.nz - 1 - kv : kv; }
+};
+
+// Face-array addressing of the VAR7 operator.
+struct Faces {
+    int nx, ny, nz;
+    __host__ __device__ int64_t ix(int i, int j, int k) const
+    {
+        return ((int64_t)k * ny + j) * (nx + 1) + i;
+    }
+    __host__ __device__ int64_t iy(int i, int j, int k) const
+    {
+        return ((int64_t)k * (ny + 1) + j) * nx + i;
+    }
+    __host__ __device__ int64_t iz(int i, int j, int k) const
+    {
+        return ((int64_t)k * ny + j) * nx + i;
+    }
+    __host__ __device__ int64_t nfx() const { return (int64_t)nz * ny * (nx + 1); }
+    __host__ __device__ int64_t nfy() const { return (int64_t)nz * (ny + 1) * nx; }
+    __host__ __device__ int64_t nfz() const { return (int64_t)(nz + 1) * ny * nx; }
+};
+
+// BLOCK7 constants passed by value: the seven 5x5 blocks, and the LU
+// factorisation with partial pivoting of the centre block (unit lower L
+// below the diagonal, U on and above; inverse pivots precomputed).
+struct Block7Consts {
+    double B[7][25];
+    double lu[25];
+    double inv_udiag[5];
+    int piv[5];
+};
+
+// Wavefront schedule of one sweep (see the sweep kernel for its meaning).
+struct SweepPlan {
+    int slab_planes;  // planes per slab (Bk)
+    int nslabs;
+    int row_slots;    // R: threads per plane in a workgroup
+    int lag_row;      // LJ
+    int lag_plane;    // LK
+    int halo_x;       // largest x offset among lower neighbours in plane k-1
+    int halo_y;       // largest y offset among lower neighbours in plane k-1
+    int threads;      // workgroup size
+    int publish_every;
+    int grid;         // workgroups launched (<= nslabs)
+};
+
+// Workspace (opaque in the ABI).
+struct Workspace {
+    m2s_kind kind;
+    m2s_dtype dtype;
+    Grid g;
+    int dev;
+    uint64_t *flags;    // nslabs_max progress flags, epoch-tagged
+    uint64_t *ticket;   // ticket counter (monotone)
+    int *err;           // device error latch
+    void *scratch;      // one vector of the stencil's size
+    void *scratch2;     // second vector (adjoint chains)
+    int64_t nflags;
+    uint32_t epoch;
+    uint64_t ticket_base;
+};
+
+constexpr int kErrTimeout = 1;
+
+}  // namespace m2s
+
+// Internal launchers implemented in the .hip files (C++ linkage, not ABI).
+namespace m2s {
+hipError_t launch_spmv(const m2s_stencil &A, const void *x, void *y,
+                       hipStream_t s);
+hipError_t launch_spmv_part(const m2s_stencil &A, int part, const void *x,
+                            void *y, hipStream_t s);
+hipError_t launch_sweep(const m2s_stencil &A, const Block7Consts *b7,
+                        double omega, const void *r, const void *xin,
+                        void *xout, bool bwd, bool zero_init, Workspace &ws,
+                        const SweepPlan &plan, hipStream_t s);
+hipError_t launch_sweep_sequential(const m2s_stencil &A, const void *r,
+                                   void *x, bool bwd, hipStream_t s);
+hipError_t launch_restrict(const m2s_stencil &A, const void *r,
+                           const void *z, void *rc, hipStream_t s);
+hipError_t launch_prolong(const m2s_stencil &Afine, const void *zc, void *z,
+                          hipStream_t s);
+hipError_t launch_var7_coarsen(m2s_dtype t, Grid fine, const void *kx,
+                               const void *ky, const void *kz, void *kxc,
+                               void *kyc, void *kzc, hipStream_t s);
+hipError_t launch_face_grad(Grid g, const double *u, const double *lam,
+                            double *gx, double *gy, double *gz,
+                            hipStream_t s);
+hipError_t launch_convert(const void *src, m2s_dtype st, void *dst,
+                          m2s_dtype dt, int64_t n, hipStream_t s);
+hipError_t launch_fill(void *dst, m2s_dtype t, int64_t n, double v,
+                       hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, int64_t bytes,
+                       hipStream_t s);
+hipError_t launch_scale(void *x, m2s_dtype t, int64_t n, double a,
+                        hipStream_t s);
+// x += y
+hipError_t launch_add(void *x, const void *y, m2s_dtype t, int64_t n,
+                      hipStream_t s);
+
+// CG vector kernels (double).  Scalars live in a small device array `sc`.
+enum CgScalar {
+    SC_RZ = 0, SC_RZ_OLD, SC_PAP, SC_RR, SC_ALPHA, SC_BETA, SC_TMP, SC_N
+};
+int dot_partials_capacity();
+hipError_t launch_dot(const double *x, const double *y, int64_t n,
+                      double *partials, double *out, hipStream_t s);
+// r = b - Ax (Ax given) and rr = r.r
+hipError_t launch_residual(const double *b, const double *ax, double *r,
+                           int64_t n, double *partials, double *rr_out,
+                           hipStream_t s);
+// p = z (first) or p = z + (rz/rz_old) p ; rz computed beforehand
+hipError_t launch_update_p(const double *z, double *p, int64_t n,
+                           const double *sc, bool first, hipStream_t s);
+// x += alpha p ; r -= alpha Ap ; rr = r.r ; alpha = rz / pAp
+hipError_t launch_update_xr(double *x, double *r, const double *p,
+                            const double *ap, int64_t n, double *sc,
+                            double *partials, hipStream_t s);
+// Ap = A p and pAp = p.Ap fused (CONST27/VAR7 double)
+hipError_t launch_spmv_dot(const m2s_stencil &A, const double *p, double *ap,
+                           double *partials, double *out, hipStream_t s);
+// x = 0 with a small fill kernel (graph-capture safe)
+}  // namespace m2s

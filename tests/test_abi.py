@@ -1,0 +1,57 @@
+"""The C-ABI library loads and exports every symbol include/m2s.h declares;
+host-only entry points behave (no GPU needed)."""
+import ctypes as C
+
+import pytest
+
+from paper_2204_13304_amd import _lib as L
+
+
+def test_library_exports_every_header_symbol():
+    lib = L.load()
+    names = L.header_symbols()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_version():
+    lib = L.load()
+    assert lib.m2s_version() >= 10000
+    for s in range(10):
+        assert lib.m2s_status_string(s)
+
+
+def test_plan_validation_errors():
+    lib = L.load()
+    p = L.SweepPlanC()
+    s = L.StencilC()
+    s.kind, s.dtype = L.CONST27, L.F64
+    s.diag, s.offdiag = 26.0, -1.0
+    s.ext = L.Extent(0, 4, 4)
+    assert lib.m2s_plan_sweep(C.byref(s), C.byref(p)) == 2  # SHAPE
+    s.ext = L.Extent(4, 4, 4)
+    s.dtype = 7
+    assert lib.m2s_plan_sweep(C.byref(s), C.byref(p)) == 3  # DTYPE
+    s.dtype = L.F64
+    s.kind = L.VAR7  # no face arrays
+    assert lib.m2s_plan_sweep(C.byref(s), C.byref(p)) == 1  # ARG
+    s.kind = L.CONST27
+    s.diag = 0.0
+    assert lib.m2s_plan_sweep(C.byref(s), C.byref(p)) == 1
+    s.diag = 26.0
+    assert lib.m2s_plan_sweep(None, C.byref(p)) == 1
+    assert lib.m2s_plan_sweep(C.byref(s), C.byref(p)) == 0
+    assert p.lag_row == 2 and p.lag_plane == 4
+    s.ext = L.Extent(4096, 4096, 4)  # more row slots than a workgroup holds
+    assert lib.m2s_plan_sweep(C.byref(s), C.byref(p)) == 2
+
+
+@pytest.mark.parametrize("n", [16, 104, 256])
+def test_plan_shapes(n):
+    import paper_2204_13304_amd as m
+    p = m.plan_sweep(m.const27((n, n, n)))
+    assert p["row_slots"] == min(n, (n + 1) // 2)
+    assert p["threads"] % 64 == 0 and p["threads"] <= 1024
+    assert p["slab_planes"] * p["row_slots"] <= p["threads"]
+    assert p["nslabs"] * p["slab_planes"] >= n

@@ -1,0 +1,125 @@
+"""GPU parity of the CONST27 SpMV and the exact lexicographic SymGS
+wavefront against the CPU oracle (relative 1e-13 in FP64), bitwise
+agreement of the wavefront with the one-thread sequential kernel, the
+residual identity of a forward sweep, and the FP32 path."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2204_13304_amd import inputs
+from tests.gpu_util import banner, dev, host, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(16, 16, 16), (9, 26, 13), (40, 17, 33), (1, 1, 1), (2, 3, 70),
+          (70, 3, 2), (5, 1, 8), (24, 24, 24)]
+
+
+@pytest.fixture(scope="module")
+def m():
+    import paper_2204_13304_amd as pkg
+    assert torch.cuda.is_available()
+    return pkg
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_spmv_parity(m, shape):
+    banner(f"spmv27 {shape}")
+    A = m.const27(shape)
+    x = inputs.standard_normal(0, shape)
+    y = host(m.spmv(A, dev(x)))
+    assert rel_inf(y, oracle.spmv27(x)) <= 1e-13
+    ones = np.ones(shape)
+    assert np.array_equal(host(m.spmv(A, dev(ones))), oracle.spmv27(ones))
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("direction", ["fwd", "bwd", "sym"])
+def test_symgs_parity_and_bitwise(m, shape, direction):
+    banner(f"symgs27 {direction} {shape}")
+    A = m.const27(shape)
+    r = inputs.standard_normal(1, shape)
+    x0 = inputs.standard_normal(2, shape)
+    ref = oracle.symgs27(r, x0, direction)
+    xg = dev(x0)
+    m.symgs(A, dev(r), xg, direction)
+    out = host(xg)
+    assert rel_inf(out, ref) <= 1e-13
+    xs = dev(x0)
+    m.symgs_sequential(A, dev(r), xs, direction)
+    assert np.array_equal(out, host(xs)), "wavefront != sequential"
+
+
+@pytest.mark.parametrize("bk", ["1", "2", "3", "8"])
+def test_symgs_slab_thickness_bitwise(m, bk, monkeypatch):
+    # every slab thickness gives the identical result (only the schedule
+    # changes, never the arithmetic)
+    monkeypatch.setenv("M2S_SLAB_PLANES", bk)
+    shape = (21, 19, 23)
+    banner(f"symgs27 slab planes {bk}")
+    A = m.const27(shape)
+    r = inputs.standard_normal(3, shape)
+    x0 = inputs.standard_normal(4, shape)
+    xg = dev(x0)
+    m.symgs(A, dev(r), xg, "sym")
+    xs = dev(x0)
+    m.symgs_sequential(A, dev(r), xs, "sym")
+    assert np.array_equal(host(xg), host(xs))
+
+
+def test_residual_identity(m):
+    # (D + L) x_new + U x_old = r for a forward sweep, evaluated on the CPU
+    shape = (12, 20, 18)
+    A = m.const27(shape)
+    r = inputs.standard_normal(5, shape)
+    x0 = inputs.standard_normal(6, shape)
+    x1 = dev(np.zeros(shape))
+    m.symgs_oop(A, dev(r), dev(x0), x1, "fwd")
+    x1 = host(x1)
+    lhs = 26.0 * x1 + oracle.spmv27_part(x1, -1) + oracle.spmv27_part(x0, +1)
+    assert np.max(np.abs(lhs - r)) <= 1e-12
+
+
+def test_zero_start_sweep(m):
+    shape = (16, 16, 16)
+    A = m.const27(shape)
+    r = inputs.standard_normal(7, shape)
+    out = dev(np.full(shape, np.nan))
+    m.symgs_oop(A, dev(r), None, out, "fwd")
+    ref = oracle.symgs27(r, np.zeros(shape), "fwd")
+    assert rel_inf(host(out), ref) <= 1e-13
+
+
+def test_float32_path(m):
+    shape = (20, 18, 22)
+    A = m.const27(shape, dtype=torch.float32)
+    r = inputs.standard_normal(8, shape)
+    x0 = inputs.standard_normal(9, shape)
+    xg = dev(x0, torch.float32)
+    m.symgs(A, dev(r, torch.float32), xg, "sym")
+    out = host(xg)
+    ref32 = oracle.symgs27(r.astype(np.float32), x0.astype(np.float32),
+                           "sym", dtype=np.float32)
+    ref64 = oracle.symgs27(r, x0, "sym")
+    assert rel_inf(out, ref32) <= 2e-6
+    assert rel_inf(out, ref64) <= 2e-6
+    y = host(m.spmv(A, dev(x0, torch.float32)))
+    assert rel_inf(y, oracle.spmv27(x0)) <= 2e-6
+
+
+@pytest.mark.parametrize("n", [104, 256])
+def test_full_size_symgs(m, n):
+    # the configuration the benchmark times, compared point by point
+    shape = (n, n, n)
+    banner(f"symgs27 full size {shape}")
+    A = m.const27(shape)
+    r = inputs.standard_normal(10, shape)
+    x0 = inputs.standard_normal(11, shape)
+    xg = dev(x0)
+    m.symgs(A, dev(r), xg, "sym")
+    out = host(xg)
+    ref = oracle.symgs27(r, x0, "sym")
+    assert rel_inf(out, ref) <= 1e-13
+    y = host(m.spmv(A, dev(x0)))
+    assert rel_inf(y, oracle.spmv27(x0)) <= 1e-13

@@ -1,0 +1,124 @@
+"""GPU parity of the multigrid V-cycle and the HPCG-form PCG against the
+oracle: V-cycle output (relative 1e-12), the 16^3 SymGS-PCG run to the known
+solution x = 1, the 104^3 4-level MG-PCG, mixed precision to 1e-9, and the
+VAR7 MG-PCG."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2204_13304_amd import inputs
+from tests.gpu_util import banner, dev, host, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m():
+    import paper_2204_13304_amd as pkg
+    assert torch.cuda.is_available()
+    return pkg
+
+
+@pytest.mark.parametrize("shape,levels", [((16, 16, 16), 3),
+                                          ((8, 24, 16), 4),
+                                          ((104, 104, 104), 4)])
+def test_vcycle_parity(m, shape, levels):
+    banner(f"vcycle {shape} L={levels}")
+    A = m.const27(shape)
+    mg = m.MG(A, levels)
+    r = inputs.standard_normal(1, shape)
+    z = host(mg.vcycle(dev(r)))
+    ref = oracle.MG("const27", shape, levels).vcycle(r)
+    assert rel_inf(z, ref) <= 1e-12
+
+
+def test_vcycle_f32(m):
+    shape = (32, 32, 32)
+    A = m.const27(shape)
+    mg = m.MG(A, 3, prec=torch.float32)
+    r = inputs.standard_normal(2, shape)
+    z = host(mg.vcycle(dev(r)))
+    ref32 = oracle.MG("const27", shape, 3, dtype=np.float32).vcycle(
+        r.astype(np.float32))
+    ref64 = oracle.MG("const27", shape, 3).vcycle(r)
+    assert rel_inf(z, ref32) <= 1e-5
+    assert rel_inf(z, ref64) <= 1e-5
+
+
+def test_pcg_symgs_small_config(m):
+    # 16^3, b = A*1, x0 = 0, 50 SymGS-preconditioned iterations
+    shape = (16, 16, 16)
+    banner("pcg symgs 16^3")
+    A = m.const27(shape)
+    b = oracle.spmv27(np.ones(shape))
+    x, info = m.pcg_solve(A, dev(b), None, "symgs", max_iter=50, rtol=0.0)
+    x = host(x)
+    assert info["iters"] == 50
+    assert np.max(np.abs(x - 1)) <= 1e-12
+    ref = oracle.pcg(b, precond="symgs", max_iter=50)
+    assert np.max(np.abs(x - ref["x"])) <= 1e-12
+    _, i9 = m.pcg_solve(A, dev(b), None, "symgs", max_iter=200, rtol=1e-9)
+    r9 = oracle.pcg(b, precond="symgs", max_iter=200, tol=1e-9)
+    assert abs(i9["iters"] - r9["iters"]) <= 1
+    assert i9["true_rel_res"] <= 1e-9
+
+
+def test_pcg_mg_104(m):
+    shape = (104, 104, 104)
+    banner("pcg mg 104^3")
+    A = m.const27(shape)
+    b = oracle.spmv27(np.ones(shape)) + inputs.rhs_perturbation(2, shape)
+    mg = m.MG(A, 4)
+    x, info = m.pcg_solve(A, dev(b), None, "mg", mg, max_iter=50, rtol=0.0,
+                          history=True)
+    ref = oracle.pcg(b, precond="mg", levels=4, max_iter=50)
+    x = host(x)
+    assert info["iters"] == 50
+    # compare the residual histories while they are above rounding level
+    h, hr = info["hist"], ref["hist"]
+    k = int(np.argmax(hr < 1e-10)) if np.any(hr < 1e-10) else len(hr)
+    assert np.allclose(h[:k], hr[:k], rtol=1e-6, atol=0)
+    assert rel_inf(x, ref["x"]) <= 1e-10
+
+
+def test_pcg_mixed_precision(m):
+    shape = (64, 64, 64)
+    banner("pcg mixed 64^3")
+    A = m.const27(shape)
+    b = oracle.spmv27(np.ones(shape)) + inputs.rhs_perturbation(3, shape)
+    mg32 = m.MG(A, 4, prec=torch.float32)
+    x32, i32 = m.pcg_solve(A, dev(b), None, "mg", mg32, max_iter=200,
+                           rtol=1e-9, replace_every=50)
+    r32 = oracle.pcg(b, precond="mg_f32", levels=4, max_iter=200, tol=1e-9,
+                     replace_every=50)
+    r64 = oracle.pcg(b, precond="mg", levels=4, max_iter=200, tol=1e-9)
+    assert i32["true_rel_res"] <= 1e-9
+    assert abs(i32["iters"] - r32["iters"]) <= 2
+    assert rel_inf(host(x32), r64["x"]) <= 1e-7
+
+
+def test_pcg_var7(m):
+    shape = (32, 32, 32)
+    banner("pcg var7 32^3")
+    pr = inputs.var7_problem(5, shape)
+    faces = [dev(pr[k]) for k in ("kx", "ky", "kz")]
+    A = m.var7(*faces)
+    mg = m.MG(A, 3)
+    u, info = m.pcg_solve(A, dev(pr["f"]), None, "mg", mg, max_iter=300,
+                          rtol=1e-10)
+    ref = oracle.pcg(pr["f"], kind="var7", faces=(pr["kx"], pr["ky"],
+                                                   pr["kz"]),
+                     precond="mg", levels=3, max_iter=300, tol=1e-10)
+    assert info["true_rel_res"] <= 1e-10
+    assert abs(info["iters"] - ref["iters"]) <= 1
+    assert rel_inf(host(u), ref["x"]) <= 1e-8
+
+
+def test_pcg_breakdown_reported(m):
+    shape = (8, 8, 8)
+    A = m.const27(shape, diag=-26.0)
+    b = dev(np.ones(shape))
+    _, info = m.pcg_solve(A, b, None, "none", max_iter=10, rtol=1e-9,
+                          raise_on_error=False)
+    assert info["status"] == "M2S_ERR_BREAKDOWN"
