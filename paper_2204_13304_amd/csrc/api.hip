@@ -58,6 +58,7 @@ struct m2s_workspace : public Workspace {};
 namespace {
 
 constexpr int kMaxThreads = 1024;
+constexpr size_t kC27MaxLds = 156 * 1024;
 
 int env_int(const char *name, int dflt)
 {
@@ -127,20 +128,29 @@ m2s_status make_plan(const m2s_stencil &A, SweepPlan &P, bool with_grid)
     P.lag_plane = c27 ? 4 : 1;
     P.halo_x = c27 ? 1 : 0;
     P.halo_y = c27 ? 1 : 0;
-    int R = (nx + P.lag_row - 1) / P.lag_row;
-    if (R > ny) R = ny;
-    if (R > kMaxThreads) return M2S_ERR_SHAPE;
-    P.row_slots = R;
-    int bk = env_int("M2S_SLAB_PLANES", 0);
-    if (bk <= 0) {
-        // default thickness: enough rows per workgroup to fill a CU without
-        // serialising too much of the plane chain on one workgroup
-        const int target_threads = A.kind == M2S_BLOCK7_5 ? 256 : 512;
-        bk = target_threads / R;
-        if (bk < 1) bk = 1;
-        if (bk > 8) bk = 8;
+    int R, bk = env_int("M2S_SLAB_PLANES", 0);
+    if (c27) {
+        // one row per thread, all ny rows of a plane in the workgroup
+        R = ny;
+        if (R > c27_max_threads() ||
+            c27_lds_bytes(1, ny, A.dtype) > kC27MaxLds)
+            return M2S_ERR_SHAPE;
+        if (bk <= 0) bk = std::max(1, 512 / R);
+        bk = std::min(bk, c27_max_threads() / R);
+        while (bk > 1 && c27_lds_bytes(bk, ny, A.dtype) > kC27MaxLds) --bk;
+    } else {
+        R = (nx + P.lag_row - 1) / P.lag_row;
+        if (R > ny) R = ny;
+        if (R > kMaxThreads) return M2S_ERR_SHAPE;
+        if (bk <= 0) {
+            // enough rows per workgroup to fill a CU without serialising too
+            // much of the plane chain on one workgroup
+            const int target = A.kind == M2S_BLOCK7_5 ? 256 : 512;
+            bk = std::max(1, std::min(8, target / R));
+        }
+        if (bk * R > kMaxThreads) bk = kMaxThreads / R;
     }
-    if (bk * R > kMaxThreads) bk = kMaxThreads / R;
+    P.row_slots = R;
     if (bk > nz) bk = nz;
     if (bk < 1) bk = 1;
     P.slab_planes = bk;
@@ -155,7 +165,11 @@ m2s_status make_plan(const m2s_stencil &A, SweepPlan &P, bool with_grid)
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
                                   dev) != hipSuccess)
             return M2S_ERR_HIP;
-        int per_cu = sweep_max_blocks_per_cu(A.kind, A.dtype, P.threads);
+        int per_cu =
+            c27 ? c27_max_blocks_per_cu(
+                      A.dtype, P.threads,
+                      c27_lds_bytes(P.slab_planes, ny, A.dtype))
+                : sweep_max_blocks_per_cu(A.kind, A.dtype, P.threads);
         int64_t cap = (int64_t)cus * per_cu;
         P.grid = (int)std::min<int64_t>(P.nslabs, cap);
         if (P.grid < 1) P.grid = 1;
@@ -172,6 +186,29 @@ m2s_status check_ws(const m2s_stencil &A, const m2s_workspace *ws)
     return M2S_OK;
 }
 
+// The 27-point sweep needs one boundary buffer per slab boundary.  Grown
+// (synchronously) only when a plan with more slabs shows up.
+m2s_status ensure_boundaries(m2s_workspace *ws, int nslabs)
+{
+    const int need = nslabs > 1 ? nslabs - 1 : 1;
+    if (ws->bnd && ws->bnd_nbuf >= need) return M2S_OK;
+    if (ws->bnd) {
+        if (hipDeviceSynchronize() != hipSuccess) return M2S_ERR_HIP;
+        (void)hipFree(ws->bnd);
+        ws->bnd = nullptr;
+    }
+    const int64_t n = (int64_t)need * c27_bnd_stride(ws->g.nx, ws->g.ny);
+    if (hipMalloc(&ws->bnd, n * (ws->dtype == M2S_F64 ? 8 : 4)) !=
+        hipSuccess)
+        return M2S_ERR_HIP;
+    if (c27_fill_sentinel(ws->bnd, ws->dtype, n, 0) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess)
+        return M2S_ERR_HIP;
+    ws->bnd_elems = n;
+    ws->bnd_nbuf = need;
+    return M2S_OK;
+}
+
 // One half-sweep out of place.
 m2s_status half_sweep(const m2s_stencil &A, const Block7Consts *b7,
                       double omega, const void *r, const void *xin,
@@ -182,6 +219,9 @@ m2s_status half_sweep(const m2s_stencil &A, const Block7Consts *b7,
     m2s_status st = make_plan(A, P, true);
     if (st != M2S_OK) return st;
     if (P.nslabs > ws->nflags) return M2S_ERR_SHAPE;
+    if (A.kind == M2S_CONST27 &&
+        (st = ensure_boundaries(ws, P.nslabs)) != M2S_OK)
+        return st;
     return hip_status(launch_sweep(A, b7, omega, r, xin, xout, bwd, zero_init,
                                    *ws, P, s));
 }
@@ -250,6 +290,15 @@ m2s_status m2s_workspace_create(const m2s_stencil *A, m2s_workspace **out)
               hipMalloc(&ws->err, sizeof(int)) == hipSuccess &&
               hipMalloc(&ws->scratch, vb) == hipSuccess &&
               hipMalloc(&ws->scratch2, vb) == hipSuccess;
+    if (ok && A->kind == M2S_CONST27) {
+        SweepPlan P{};
+        const m2s_status pst = make_plan(*A, P, false);
+        if (pst != M2S_OK) {
+            m2s_workspace_destroy(ws);
+            return pst;
+        }
+        ok = ensure_boundaries(ws, P.nslabs) == M2S_OK;
+    }
     ok = ok && hipMemset(ws->flags, 0, sizeof(uint64_t) * ws->nflags) ==
                    hipSuccess &&
          hipMemset(ws->ticket, 0, sizeof(uint64_t)) == hipSuccess &&
@@ -272,6 +321,7 @@ void m2s_workspace_destroy(m2s_workspace *ws)
     if (ws->err) (void)hipFree(ws->err);
     if (ws->scratch) (void)hipFree(ws->scratch);
     if (ws->scratch2) (void)hipFree(ws->scratch2);
+    if (ws->bnd) (void)hipFree(ws->bnd);
     delete ws;
 }
 
@@ -290,6 +340,9 @@ m2s_status m2s_check(m2s_workspace *ws, hipStream_t stream)
         if (hipMemcpy(&tk, ws->ticket, sizeof(tk), hipMemcpyDeviceToHost) !=
                 hipSuccess ||
             hipMemset(ws->err, 0, sizeof(int)) != hipSuccess)
+            return M2S_ERR_HIP;
+        if (ws->bnd && c27_fill_sentinel(ws->bnd, ws->dtype, ws->bnd_elems,
+                                         0) != hipSuccess)
             return M2S_ERR_HIP;
         if (hipDeviceSynchronize() != hipSuccess) return M2S_ERR_HIP;
         ws->ticket_base = tk;
@@ -688,6 +741,9 @@ m2s_status workspace_error(m2s_workspace *ws)
         uint64_t tk = 0;
         (void)hipMemcpy(&tk, ws->ticket, sizeof(tk), hipMemcpyDeviceToHost);
         (void)hipMemset(ws->err, 0, sizeof(int));
+        if (ws->bnd)
+            (void)c27_fill_sentinel(ws->bnd, ws->dtype, ws->bnd_elems, 0);
+        (void)hipDeviceSynchronize();
         ws->ticket_base = tk;
         return M2S_ERR_TIMEOUT;
     }

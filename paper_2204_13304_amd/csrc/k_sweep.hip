@@ -383,11 +383,7 @@ hipError_t launch_sweep(const m2s_stencil &A, const Block7Consts *b7,
     if (zero_init) xin = nullptr;
     switch (A.kind) {
     case M2S_CONST27:
-        return A.dtype == M2S_F64
-                   ? launch_typed<KIND_C27, double>(A, b7, omega, r, xin,
-                                                    xout, bwd, ws, plan, s)
-                   : launch_typed<KIND_C27, float>(A, b7, omega, r, xin, xout,
-                                                   bwd, ws, plan, s);
+        return launch_sweep27(A, r, xin, xout, bwd, ws, plan, s);
     case M2S_VAR7:
         return A.dtype == M2S_F64
                    ? launch_typed<KIND_V7, double>(A, b7, omega, r, xin, xout,

@@ -94,6 +94,9 @@ struct Workspace {
     int *err;           // device error latch
     void *scratch;      // one vector of the stencil's size
     void *scratch2;     // second vector (adjoint chains)
+    void *bnd;          // 27-point sweep: per-boundary buffers (NaN-boxed)
+    int64_t bnd_elems;
+    int bnd_nbuf;       // boundary buffers allocated
     int64_t nflags;
     uint32_t epoch;
     uint64_t ticket_base;
@@ -136,6 +139,17 @@ hipError_t launch_scale(void *x, m2s_dtype t, int64_t n, double a,
 // x += y
 hipError_t launch_add(void *x, const void *y, m2s_dtype t, int64_t n,
                       hipStream_t s);
+
+// 27-point wavefront sweep (k_sweep27.hip).
+hipError_t launch_sweep27(const m2s_stencil &A, const void *r,
+                          const void *xin, void *xout, bool bwd,
+                          Workspace &ws, const SweepPlan &plan,
+                          hipStream_t s);
+int c27_max_threads();
+int64_t c27_bnd_stride(int nx, int ny);
+size_t c27_lds_bytes(int Bk, int R, m2s_dtype t);
+hipError_t c27_fill_sentinel(void *p, m2s_dtype t, int64_t n, hipStream_t s);
+int c27_max_blocks_per_cu(m2s_dtype t, int threads, size_t lds);
 
 // CG vector kernels (double).  Scalars live in a small device array `sc`.
 enum CgScalar {

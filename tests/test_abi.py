@@ -43,7 +43,7 @@ def test_plan_validation_errors():
     assert lib.m2s_plan_sweep(None, C.byref(p)) == 1
     assert lib.m2s_plan_sweep(C.byref(s), C.byref(p)) == 0
     assert p.lag_row == 2 and p.lag_plane == 4
-    s.ext = L.Extent(4096, 4096, 4)  # more row slots than a workgroup holds
+    s.ext = L.Extent(64, 2048, 4)  # more rows than a workgroup holds
     assert lib.m2s_plan_sweep(C.byref(s), C.byref(p)) == 2
 
 
@@ -51,7 +51,8 @@ def test_plan_validation_errors():
 def test_plan_shapes(n):
     import paper_2204_13304_amd as m
     p = m.plan_sweep(m.const27((n, n, n)))
-    assert p["row_slots"] == min(n, (n + 1) // 2)
+    # 27 points: one thread per row of a plane
+    assert p["row_slots"] == n
     assert p["threads"] % 64 == 0 and p["threads"] <= 1024
     assert p["slab_planes"] * p["row_slots"] <= p["threads"]
     assert p["nslabs"] * p["slab_planes"] >= n

@@ -139,6 +139,17 @@ def test_gpu_schedule_satisfies_all_dependences(kind, shape, bk, monkeypatch):
                     ta, Ka = step[a], slab[a]
                     if Ka == K:
                         assert ta < t, (a, (k, j, i))
+                    elif c27:
+                        # the 27-point kernel hands the previous slab's top
+                        # plane over value by value: row j' of plane k0-1 is
+                        # staged at column i' one step before its first read
+                        # (at local step i' + 2j' - 3, by row j'-1) and the
+                        # stage waits until the value has been written
+                        assert Ka == K - 1
+                        _, jp, ip = a
+                        stage_step = ip - 4 + 2 * jp
+                        first_read = ip + 2 * jp - 3
+                        assert stage_step < first_read <= t
                     else:
                         # producer slab must be exactly the previous one and
                         # covered by the progress wait of the G-window
