@@ -1,0 +1,98 @@
+"""GPU parity of the BLOCK7x5 SpMV and the block SSOR half-sweeps (NPB-LU
+shaped, omega = 1.2) against the oracle, bitwise agreement between slab
+thicknesses, and the 162^3 x 5 configuration point by point."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2204_13304_amd import inputs
+from tests.gpu_util import banner, dev, host, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(6, 7, 8), (13, 5, 9), (1, 1, 1), (2, 9, 3), (17, 17, 17)]
+
+
+@pytest.fixture(scope="module")
+def m():
+    import paper_2204_13304_amd as pkg
+    assert torch.cuda.is_available()
+    return pkg
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_spmv_block7(m, shape):
+    B = inputs.block7_blocks(4)
+    A = m.block7(shape, B)
+    x = inputs.standard_normal(1, shape + (5,))
+    y = host(m.spmv(A, dev(x)))
+    assert rel_inf(y, oracle.spmv_block7(x, B)) <= 1e-13
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("direction", ["fwd", "bwd", "sym"])
+def test_ssor_parity(m, shape, direction):
+    banner(f"ssor {direction} {shape}")
+    B = inputs.block7_blocks(4)
+    A = m.block7(shape, B)
+    b = inputs.standard_normal(2, shape + (5,))
+    x0 = inputs.standard_normal(3, shape + (5,))
+    xg = dev(x0)
+    m.ssor_sweep(A, dev(b), xg, 1.2, direction)
+    ref = oracle.ssor_block7(b, x0, B, 1.2, direction)
+    assert rel_inf(host(xg), ref) <= 1e-13
+
+
+@pytest.mark.parametrize("bk", ["1", "3"])
+def test_ssor_slab_thickness_bitwise(m, bk, monkeypatch):
+    shape = (11, 9, 10)
+    B = inputs.block7_blocks(4)
+    A = m.block7(shape, B)
+    b = dev(inputs.standard_normal(4, shape + (5,)))
+    x0 = inputs.standard_normal(5, shape + (5,))
+    outs = []
+    for planes in (bk, "2"):
+        monkeypatch.setenv("M2S_SLAB_PLANES", planes)
+        xg = dev(x0)
+        m.ssor_sweep(A, b, xg, 1.2, "sym")
+        outs.append(host(xg))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_ssor_iterations_converge(m):
+    # 20 SSOR iterations from x0 = 0 on b = A*1 approach x = 1
+    shape = (12, 12, 12)
+    B = inputs.block7_blocks(4)
+    A = m.block7(shape, B)
+    b = m.spmv(A, dev(np.ones(shape + (5,))))
+    x = torch.zeros_like(b)
+    for _ in range(20):
+        m.ssor_sweep(A, b, x, 1.2, "sym")
+    ref = np.zeros(shape + (5,))
+    bh = host(b)
+    for _ in range(20):
+        ref = oracle.ssor_block7(bh, ref, B, 1.2, "sym")
+    assert rel_inf(host(x), ref) <= 1e-12
+    assert np.max(np.abs(host(x) - 1)) < 1e-6
+
+
+def test_full_size_ssor_162(m):
+    # the NPB-LU-shaped configuration: one SSOR iteration at 162^3 x 5
+    shape = (162, 162, 162)
+    banner("ssor 162^3 x 5")
+    B = inputs.block7_blocks(4)
+    A = m.block7(shape, B)
+    ones = np.ones(shape + (5,))
+    b = oracle.spmv_block7(ones, B)
+    xg = torch.zeros(shape + (5,), dtype=torch.float64, device="cuda")
+    m.ssor_sweep(A, dev(b), xg, 1.2, "sym")
+    ref = oracle.ssor_block7(b, np.zeros_like(b), B, 1.2, "sym")
+    assert rel_inf(host(xg), ref) <= 1e-13
+
+
+def test_ssor_rejects_bad_omega(m):
+    A = m.block7((4, 4, 4), inputs.block7_blocks(4))
+    x = torch.zeros((4, 4, 4, 5), dtype=torch.float64, device="cuda")
+    with pytest.raises(RuntimeError):
+        m.ssor_sweep(A, x.clone(), x, 2.5, "sym")

@@ -1,0 +1,159 @@
+"""GPU parity of the VAR7 operator (SpMV, sweeps, strict parts), the sweep
+adjoints (dot-product identity against the forward sweep), the face-
+coefficient gradient kernel, and the autograd solve (adjoint MG-PCG +
+face gradient) against finite differences and the oracle gradient."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2204_13304_amd import inputs
+from tests.gpu_util import banner, dev, host, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(8, 8, 8), (5, 9, 13), (16, 16, 16), (1, 3, 7)]
+
+
+@pytest.fixture(scope="module")
+def m():
+    import paper_2204_13304_amd as pkg
+    assert torch.cuda.is_available()
+    return pkg
+
+
+def _A(m, pr, dtype=torch.float64):
+    return m.var7(*(dev(pr[k], dtype) for k in ("kx", "ky", "kz")))
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_spmv_and_parts(m, shape):
+    pr = inputs.var7_problem(21, shape)
+    A = _A(m, pr)
+    x = inputs.standard_normal(1, shape)
+    f = (pr["kx"], pr["ky"], pr["kz"])
+    assert rel_inf(host(m.spmv(A, dev(x))), oracle.spmv_var7(x, *f)) <= 1e-13
+    for part in (-1, 1):
+        assert rel_inf(host(m.spmv_part(A, dev(x), part)),
+                       oracle.spmv_var7_part(x, *f, part)) <= 1e-13
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("direction", ["fwd", "bwd", "sym"])
+def test_symgs_var7(m, shape, direction):
+    banner(f"var7 symgs {direction} {shape}")
+    pr = inputs.var7_problem(22, shape)
+    A = _A(m, pr)
+    r = inputs.standard_normal(2, shape)
+    x0 = inputs.standard_normal(3, shape)
+    xg = dev(x0)
+    m.symgs(A, dev(r), xg, direction)
+    ref = oracle.symgs_var7(r, x0, pr["kx"], pr["ky"], pr["kz"], direction)
+    out = host(xg)
+    assert rel_inf(out, ref) <= 1e-13
+    xs = dev(x0)
+    m.symgs_sequential(A, dev(r), xs, direction)
+    assert np.array_equal(out, host(xs))
+
+
+def test_var7_float32(m):
+    shape = (12, 10, 14)
+    pr = inputs.var7_problem(23, shape)
+    A = _A(m, pr, torch.float32)
+    r = inputs.standard_normal(4, shape)
+    xg = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    m.symgs(A, dev(r, torch.float32), xg, "sym")
+    ref = oracle.symgs_var7(r, np.zeros(shape), pr["kx"], pr["ky"],
+                            pr["kz"], "sym")
+    assert rel_inf(host(xg), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("kind", ["const27", "var7"])
+@pytest.mark.parametrize("direction", ["fwd", "bwd", "sym"])
+def test_sweep_adjoint_dot_identity(m, kind, direction):
+    # <g, S(r, x)> = <gr, r> + <gx, x> for the linear map (r, x) -> S(r, x)
+    shape = (9, 10, 11)
+    if kind == "const27":
+        A = m.const27(shape)
+    else:
+        A = _A(m, inputs.var7_problem(24, shape))
+    r = dev(inputs.standard_normal(5, shape))
+    x = dev(inputs.standard_normal(6, shape))
+    g = dev(inputs.standard_normal(7, shape))
+    s = x.clone()
+    m.symgs(A, r, s, direction)
+    gr, gx = m.symgs_adjoint(A, g, direction)
+    lhs = torch.dot(g.ravel(), s.ravel()).item()
+    rhs = (torch.dot(gr.ravel(), r.ravel()) +
+           torch.dot(gx.ravel(), x.ravel())).item()
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+
+
+def test_symgs_autograd_function(m):
+    shape = (7, 8, 9)
+    A = m.const27(shape)
+    r = dev(inputs.standard_normal(8, shape)).requires_grad_(True)
+    x = dev(inputs.standard_normal(9, shape)).requires_grad_(True)
+    w = dev(inputs.standard_normal(10, shape))
+    y = m.symgs_fn(A, r, x, "sym")
+    (y * w).sum().backward()
+    gr, gx = m.symgs_adjoint(A, w, "sym")
+    assert torch.equal(r.grad, gr) and torch.equal(x.grad, gx)
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (7, 9, 11)])
+def test_face_grad_parity(m, shape):
+    pr = inputs.var7_problem(25, shape)
+    A = _A(m, pr)
+    u = inputs.standard_normal(11, shape)
+    lam = inputs.standard_normal(12, shape)
+    g = m.face_grad(A, dev(u), dev(lam))
+    ref = oracle.var7_face_grad(u, lam)
+    for a, b in zip(g, ref):
+        assert rel_inf(host(a), b) <= 1e-14
+
+
+def _loss(m, kx, ky, kz, f, ut, levels, rtol):
+    u = m.solve(kx, ky, kz, f, levels=levels, rtol=rtol, max_iter=500)
+    return 0.5 * ((u - ut) ** 2).sum(), u
+
+
+def test_solve_gradient_fd_and_oracle(m):
+    # 16^3 instance (seed 55), solved to 1e-13 so the finite differences
+    # measure the gradient, not the solver tolerance
+    shape = (16, 16, 16)
+    banner("autograd solve 16^3")
+    pr = inputs.var7_problem(55, shape)
+    kx, ky, kz = (dev(pr[k]).requires_grad_(True) for k in ("kx", "ky",
+                                                            "kz"))
+    f = dev(pr["f"]).requires_grad_(True)
+    ut = dev(pr["u_t"])
+    L, u = _loss(m, kx, ky, kz, f, ut, 3, 1e-13)
+    L.backward()
+    # oracle gradient: u, lambda by oracle PCG, face gradient by the oracle
+    faces = (pr["kx"], pr["ky"], pr["kz"])
+    uo = oracle.pcg(pr["f"], kind="var7", faces=faces, precond="mg",
+                    levels=3, max_iter=500, tol=1e-13)["x"]
+    lo = oracle.pcg(uo - pr["u_t"], kind="var7", faces=faces, precond="mg",
+                    levels=3, max_iter=500, tol=1e-13)["x"]
+    gref = oracle.var7_face_grad(uo, lo)
+    for t, gr in zip((kx, ky, kz), gref):
+        assert rel_inf(host(t.grad), gr) <= 1e-8
+    assert rel_inf(host(f.grad), lo) <= 1e-8
+    # finite differences on a few faces and right-hand-side entries
+    h = 1e-6
+    rng = np.random.default_rng(1)
+    with torch.no_grad():
+        for t in (kx, ky, kz, f):
+            for _ in range(3):
+                idx = tuple(int(rng.integers(0, s)) for s in t.shape)
+                old = t[idx].item()
+                t[idx] = old + h
+                Lp, _ = _loss(m, kx, ky, kz, f, ut, 3, 1e-13)
+                t[idx] = old - h
+                Lm, _ = _loss(m, kx, ky, kz, f, ut, 3, 1e-13)
+                t[idx] = old
+                fd = (Lp.item() - Lm.item()) / (2 * h)
+                gv = t.grad[idx].item()
+                assert abs(fd - gv) <= 1e-5 * max(1.0, abs(fd)), (idx, fd,
+                                                                 gv)
