@@ -1,52 +1,81 @@
 #!/usr/bin/env python3
 """Benchmark of the Mat2Stencil hot path on one MI355X.
 
-Workload (default): the 256^3 HPCG-style 27-point operator with a 4-level
-multigrid V-cycle (1 pre- and 1 post-SymGS per level, injection transfers)
-preconditioning CG; b = A*1 + N(0, 1e-3) (seed 3), x0 = 0.  Synthetic
-stand-in for HPCG; no dataset involved.
+Workload: the HPCG-style 27-point operator (diag 26, off-diagonal -1,
+Dirichlet) on a 256^3 grid, FP64; a 4-level multigrid V-cycle (1 pre- and
+1 post-SymGS per level, injection transfers, SymGS coarse solve) as the
+preconditioner of CG; b = A*1 + N(0, 1e-3) (seed 3), x0 = 0.  Synthetic
+stand-in for HPCG (the paper uses no dataset).
 
-A "step" is one MG-PCG iteration (V-cycle: 8 level-0 half-sweeps' worth of
-SymGS plus SpMV, restriction, prolongation on every level; top-level SpMV,
-three dot products and three vector updates).  `value` is GFLOP/s in the
-HPCG convention (2 flops per stored non-zero per SpMV or sweep direction,
-2 per vector element per dot/axpy) over the timed steps.
+A "step" is one MG-PCG iteration: the V-cycle (SymGS sweeps, fused
+residual+restriction and prolongation on every level) plus the top-level
+SpMV, three dot products and three vector updates.  `value` is GFLOP/s in
+the HPCG convention (2 flops per stored non-zero per SpMV or sweep
+direction; 2 per element per dot/axpy), over the timed steps.
 
 Also reported on the same line:
-  roofline      the exact lexicographic SymGS wavefront kernel at 256^3
-                (forward half-sweep out of place: algorithmic 24 B/point),
-                timed with HIP events on its stream, against 8 TB/s;
-  spmv          the 27-point SpMV kernel (16 B/point) likewise;
-  time_to_solution  FP64 MG-PCG and mixed-precision MG-PCG (FP32 V-cycle,
-                FP64 CG) to relative residual 1e-9 from x0 = 0;
-  cpu_baseline  the CPU oracle (single thread) on a bounded sample.
+  roofline          the exact lexicographic SymGS wavefront kernel at 256^3
+                    (forward and backward half-sweeps out of place,
+                    algorithmic 24 B per point), timed with HIP events on
+                    the stream it runs on, against 8 TB/s;
+  spmv              the 27-point SpMV kernel (16 B per point) likewise;
+  time_to_solution  FP64 MG-PCG and mixed MG-PCG (V-cycle in FP32, CG in
+                    FP64) to relative residual 1e-9 from x0 = 0;
+  cpu_baseline      the CPU oracle (one thread) on one MG-PCG iteration.
 
-    python bench.py [--gpus 1] [--steps 50] [--warmup 3]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 2]
+    python bench.py --roofline-only      (kernel loops only, for profiling)
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+SWEEP_PROFILE = os.path.join(ROOT, "profiles", "c27_sweep_256.md")
+
+
+def measured_traffic(profile=SWEEP_PROFILE):
+    """HBM bytes per launch of the sweep kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
+    the kernel source has changed since those counters were taken."""
+    try:
+        fields = {}
+        with open(profile) as fh:
+            for line in fh:
+                k, _, v = line.partition(":")
+                if k.strip() in ("kernel_source", "kernel_source_sha256",
+                                 "traffic_bytes_per_launch"):
+                    fields[k.strip()] = v.strip()
+        with open(os.path.join(ROOT, fields["kernel_source"]), "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()
+        if digest != fields["kernel_source_sha256"]:
+            return None
+        return int(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--levels", type=int, default=4)
+    ap.add_argument("--reps", type=int, default=10,
+                    help="launches per kernel in the roofline loops")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU-oracle baseline")
     ap.add_argument("--no-tts", action="store_true",
                     help="skip the time-to-solution runs")
     ap.add_argument("--roofline-only", action="store_true",
-                    help="only the kernel roofline loops (for profiling)")
+                    help="only the kernel loops and a copy calibration")
     return ap.parse_args()
 
 
@@ -73,10 +102,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def event_time_ms(torch, fn, reps):
+def event_ms(torch, fn, reps):
+    """Average duration of fn() over reps launches, HIP events recorded on
+    torch's current stream -- the stream the library launches on."""
     s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(
-        enable_timing=True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(reps):
         fn()
@@ -85,14 +116,49 @@ def event_time_ms(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def roofline_loops(torch, m, inputs, n, reps, dev):
+    shape = (n, n, n)
+    npts = n ** 3
+    A = m.const27(shape)
+    ws = m.Workspace(A)
+    r = torch.from_numpy(inputs.standard_normal(10, shape)).to(dev)
+    x0 = torch.from_numpy(inputs.standard_normal(11, shape)).to(dev)
+    x1 = torch.empty_like(x0)
+    for d in ("fwd", "bwd"):
+        m.symgs_oop(A, r, x0, x1, d, ws)  # warm
+    fwd = event_ms(torch, lambda: m.symgs_oop(A, r, x0, x1, "fwd", ws), reps)
+    bwd = event_ms(torch, lambda: m.symgs_oop(A, r, x0, x1, "bwd", ws), reps)
+    ws.check()
+    m.spmv(A, x0, x1)
+    spmv = event_ms(torch, lambda: m.spmv(A, x0, x1), reps)
+    # the same sweep in FP32 (the mixed-precision V-cycle's level 0)
+    A32 = m.const27(shape, dtype=torch.float32)
+    ws32 = m.Workspace(A32)
+    r32, x032 = r.float(), x0.float()
+    x132 = torch.empty_like(x032)
+    m.symgs_oop(A32, r32, x032, x132, "fwd", ws32)
+    fwd32 = event_ms(torch, lambda: m.symgs_oop(A32, r32, x032, x132, "fwd",
+                                                 ws32), reps)
+    ws32.check()
+    sweep_ms = 0.5 * (fwd + bwd)
+    return dict(
+        sweep_ms=sweep_ms, fwd_ms=fwd, bwd_ms=bwd, spmv_ms=spmv,
+        fwd32_ms=fwd32,
+        sweep_gbs=24 * npts / (sweep_ms * 1e-3) / 1e9,
+        spmv_gbs=16 * npts / (spmv * 1e-3) / 1e9,
+        fwd32_gbs=12 * npts / (fwd32 * 1e-3) / 1e9,
+        symgs_gflops=4 * nnz27(n) / (2 * sweep_ms * 1e-3) / 1e9,
+        spmv_gflops=2 * nnz27(n) / (spmv * 1e-3) / 1e9)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; "
-                          "--gpus must be 1 (multi-GPU sharding is "
-                          "described in DESIGN.md, not implemented)"}))
+                          "--gpus must be 1 (how the path would shard over "
+                          "several GPUs is described in DESIGN.md)"}))
         return 2
-    import numpy as np
+    import numpy as np  # noqa: F401
     import torch
 
     import paper_2204_13304_amd as m
@@ -104,39 +170,36 @@ def main():
     dev = torch.device("cuda:0")
     n, L = args.n, args.levels
     shape = (n, n, n)
-    npts = n ** 3
-    log(f"setup {shape} levels={L}")
-    A = m.const27(shape)
-    ones = torch.ones(shape, dtype=torch.float64, device=dev)
-    b = m.spmv(A, ones)
-    b += torch.from_numpy(inputs.rhs_perturbation(3, shape)).to(dev)
-    torch.cuda.synchronize()
 
-    # ---------------------------------------------------------- roofline
-    ws = m.Workspace(A)
-    r = torch.from_numpy(inputs.standard_normal(10, shape)).to(dev)
-    x0 = torch.from_numpy(inputs.standard_normal(11, shape)).to(dev)
-    x1 = torch.empty_like(x0)
-    for _ in range(3):
-        m.symgs_oop(A, r, x0, x1, "fwd", ws)
-    reps = 20
-    sweep_ms = event_time_ms(torch, lambda: m.symgs_oop(A, r, x0, x1, "fwd",
-                                                         ws), reps)
-    ws.check()
-    sweep_bytes = 24 * npts
-    sweep_gbs = sweep_bytes / (sweep_ms * 1e-3) / 1e9
-    spmv_ms = event_time_ms(torch, lambda: m.spmv(A, x0, x1), reps)
-    spmv_gbs = 16 * npts / (spmv_ms * 1e-3) / 1e9
-    log(f"sweep {sweep_ms:.3f} ms {sweep_gbs:.0f} GB/s; spmv {spmv_ms:.3f} ms "
-        f"{spmv_gbs:.0f} GB/s")
+    log(f"roofline loops at {n}^3, {args.reps} launches each")
+    rl = roofline_loops(torch, m, inputs, n, args.reps, dev)
+    log(f"sweep fwd {rl['fwd_ms']:.3f} ms bwd {rl['bwd_ms']:.3f} ms "
+        f"({rl['sweep_gbs']:.0f} GB/s); spmv {rl['spmv_ms']:.3f} ms "
+        f"({rl['spmv_gbs']:.0f} GB/s); fp32 fwd {rl['fwd32_ms']:.3f} ms")
+    roof = {"bound": "hbm", "achieved": rl["sweep_gbs"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": rl["sweep_gbs"] / HBM_PEAK_GBS,
+            "traffic": measured_traffic(),
+            "kernel": f"c27_slab_kernel<double> (fwd and bwd) at {n}^3, "
+                      "24 B/point",
+            "avg_ms": rl["sweep_ms"], "fwd_ms": rl["fwd_ms"],
+            "bwd_ms": rl["bwd_ms"]}
     if args.roofline_only:
-        print(json.dumps({"sweep_ms": sweep_ms, "spmv_ms": spmv_ms}))
+        # a plain copy of known size, for scaling the HBM byte counters
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"roofline": roof, "spmv_ms": rl["spmv_ms"],
+                          "copy_calibration_bytes_each_way": 8 << 27}))
         return 0
 
-    # ---------------------------------------------------------- steps
+    A = m.const27(shape)
+    b = m.spmv(A, torch.ones(shape, dtype=torch.float64, device=dev))
+    b += torch.from_numpy(inputs.rhs_perturbation(3, shape)).to(dev)
     mg = m.MG(A, L)
     x = torch.zeros_like(b)
-    log(f"warmup {args.warmup}")
+    log(f"warmup {args.warmup} MG-PCG iterations")
     if args.warmup > 0:
         m.pcg_solve(A, b, x, "mg", mg, max_iter=args.warmup, rtol=0.0)
     x.zero_()
@@ -148,38 +211,36 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     gflops = flops_per_iteration(n, L) * args.steps / (t1 - t0) / 1e9
-    log(f"{ms_per_step:.3f} ms/iteration, {gflops:.1f} GFLOP/s, "
+    log(f"{ms_per_step:.3f} ms/iteration, {gflops:.2f} GFLOP/s, "
         f"relres {info['rel_res']:.3e}")
 
-    # ---------------------------------------------------------- TTS
     tts = None
     if not args.no_tts:
-        out = {}
+        res = {}
         for tag, prec, rep in (("fp64", torch.float64, 0),
                                ("mixed", torch.float32, 50)):
             mgp = m.MG(A, L, prec=prec)
             xs = torch.zeros_like(b)
-            m.pcg_solve(A, b, xs, "mg", mgp, max_iter=2, rtol=0.0)  # warm
+            m.pcg_solve(A, b, xs, "mg", mgp, max_iter=1, rtol=0.0)  # warm
             xs.zero_()
             torch.cuda.synchronize()
             ta = time.perf_counter()
-            _, inf = m.pcg_solve(A, b, xs, "mg", mgp, max_iter=500,
+            _, inf = m.pcg_solve(A, b, xs, "mg", mgp, max_iter=1000,
                                  rtol=1e-9, replace_every=rep)
             torch.cuda.synchronize()
             tb = time.perf_counter()
-            out[tag] = dict(seconds=tb - ta, iters=inf["iters"],
+            res[tag] = dict(seconds=tb - ta, iters=inf["iters"],
                             true_rel_res=inf["true_rel_res"])
-            out[tag + "_x"] = xs
-            log(f"tts {tag}: {tb - ta:.4f} s, {inf['iters']} it, "
-                f"true relres {inf['true_rel_res']:.2e}")
-        err = (out["mixed_x"] - out["fp64_x"]).abs().max().item() / \
-            out["fp64_x"].abs().max().item()
-        tts = dict(rtol=1e-9, fp64=out["fp64"], mixed=out["mixed"],
-                   speedup_mixed=out["fp64"]["seconds"] /
-                   out["mixed"]["seconds"],
-                   mixed_vs_fp64_rel_err=err)
+            res[tag + "_x"] = xs
+            log(f"time to 1e-9, {tag}: {tb - ta:.3f} s, {inf['iters']} "
+                f"iterations, true relres {inf['true_rel_res']:.2e}")
+        err = ((res["mixed_x"] - res["fp64_x"]).abs().max() /
+               res["fp64_x"].abs().max()).item()
+        tts = dict(rtol=1e-9, fp64=res["fp64"], mixed=res["mixed"],
+                   speedup_mixed=res["fp64"]["seconds"] /
+                   res["mixed"]["seconds"],
+                   mixed_vs_fp64_solution_rel_err=err)
 
-    # ---------------------------------------------------------- CPU
     cpu = None
     if not args.no_cpu:
         try:
@@ -194,16 +255,17 @@ def main():
             per_it = max(1e-9, (tc - tb) - (tb - ta))
             cpu = {"value": flops_per_iteration(n, L) / per_it / 1e9,
                    "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-                   "sample": f"one MG-PCG iteration at {n}^3 (difference "
-                             "of a 2-iteration and a 1-iteration oracle "
-                             f"run; {per_it:.2f} s per iteration)"}
-        except Exception as e:  # report, do not hide
+                   "sample": f"one MG-PCG iteration at {n}^3 (difference of "
+                             "a 2-iteration and a 1-iteration oracle run, "
+                             f"{per_it:.2f} s per iteration; host has "
+                             f"{os.cpu_count()} CPUs, the oracle uses one)"}
+        except Exception as e:  # reported, not hidden
             cpu = {"error": repr(e)}
 
     line = {
         "metric": "SymGS+SpMV GFLOP/s (HPCG convention) in 256^3 MG-PCG; "
-                  "% HBM roofline of the SymGS sweep; MG-PCG time-to-1e-9 "
-                  "FP64 vs mixed",
+                  "% HBM roofline of the SymGS sweep kernel; MG-PCG "
+                  "time-to-1e-9 FP64 vs mixed",
         "value": gflops,
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -215,17 +277,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"const27 {n}^3 {L}-level MG-PCG, b = A*1 + "
+        "config": {"workload": f"const27 {n}^3, {L}-level MG-PCG, b = A*1 + "
                                "N(0,1e-3) seed 3, x0 = 0",
                    "grid": [n, n, n], "levels": L},
-        "roofline": {"bound": "hbm", "achieved": sweep_gbs,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": sweep_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "sweep_wave_kernel<CONST27,double,fwd> "
-                               f"{n}^3, 24 B/point",
-                     "avg_ms": sweep_ms},
-        "spmv": {"achieved": spmv_gbs, "unit": "GB/s", "avg_ms": spmv_ms,
-                 "frac": spmv_gbs / HBM_PEAK_GBS},
+        "roofline": roof,
+        "spmv": {"achieved": rl["spmv_gbs"], "unit": "GB/s",
+                 "avg_ms": rl["spmv_ms"],
+                 "frac": rl["spmv_gbs"] / HBM_PEAK_GBS,
+                 "gflops": rl["spmv_gflops"]},
+        "symgs_gflops": rl["symgs_gflops"],
+        "sweep_fp32": {"avg_ms": rl["fwd32_ms"], "achieved": rl["fwd32_gbs"],
+                       "unit": "GB/s"},
         "time_to_solution": tts,
         "cpu_baseline": cpu,
     }
