@@ -267,12 +267,19 @@ m2s_status m2s_convert(const void *src, m2s_dtype src_t, void *dst,
                        m2s_dtype dst_t, int64_t n, hipStream_t stream);
 
 /* ---------------------------------------------------------------------
- * Schedule of the wavefront sweep (host only, no GPU needed): the slab
- * thickness in planes, number of slabs, row slots per plane (threads per
- * plane in a workgroup), the per-row and per-plane skew of the hyperplane
- * and the number of local steps of a full slab.  Exposed so the schedule's
- * legality (every dependence from a strictly earlier step) can be checked
- * on the CPU.
+ * Schedule of the wavefront sweep (host only, no GPU needed), exposed so
+ * the schedule's legality (every dependence from a strictly earlier step)
+ * can be checked on the CPU.  Point (i, j, k) runs at step
+ * i + lag_row*j + lag_plane*k (the hyperplane of Sec. 6.1.3).
+ * M2S_CONST27: the grid's rows (j, k) are cut into tiles of row_slots = 16
+ *   consecutive u = j + k by slab_planes consecutive k (4 per wavefront),
+ *   one lane per row; nslabs = number of tiles holding a grid row, taken in
+ *   lexicographic (k-tile, u-tile) order; steps = steps of a full tile.
+ * M2S_VAR7, M2S_BLOCK7_5: slabs of slab_planes whole planes, row_slots
+ *   threads per plane; nslabs = number of slabs; steps = local steps of a
+ *   full slab.
+ * threads = workgroup size; publish_every = progress-publication interval
+ * of the slab schedule.
  * --------------------------------------------------------------------- */
 typedef struct {
     int32_t slab_planes, nslabs, row_slots, lag_row, lag_plane, steps;

@@ -58,7 +58,6 @@ struct m2s_workspace : public Workspace {};
 namespace {
 
 constexpr int kMaxThreads = 1024;
-constexpr size_t kC27MaxLds = 156 * 1024;
 
 int env_int(const char *name, int dflt)
 {
@@ -130,14 +129,38 @@ m2s_status make_plan(const m2s_stencil &A, SweepPlan &P, bool with_grid)
     P.halo_y = c27 ? 1 : 0;
     int R, bk = env_int("M2S_SLAB_PLANES", 0);
     if (c27) {
-        // one row per thread, all ny rows of a plane in the workgroup
-        R = ny;
-        if (R > c27_max_threads() ||
-            c27_lds_bytes(1, ny, A.dtype) > kC27MaxLds)
+        // tiles of 16 u = j + k rows by 4 * nw planes, one lane per row;
+        // buffer loads address a vector with 32-bit byte offsets
+        if ((int64_t)nx * ny * nz * elem_size(A) >= ((int64_t)1 << 31))
             return M2S_ERR_SHAPE;
-        if (bk <= 0) bk = std::max(1, 512 / R);
-        bk = std::min(bk, c27_max_threads() / R);
-        while (bk > 1 && c27_lds_bytes(bk, ny, A.dtype) > kC27MaxLds) --bk;
+        // 4 wavefronts (16 planes) per tile: fewest tile crossings along
+        // the k chain; small grids gain nothing from smaller tiles
+        int nw = env_int("M2S_C27_WAVES", 4);
+        if (nw != 1 && nw != 2 && nw != 4) nw = 4;
+        const C27Layout L = c27_layout(Grid{nx, ny, nz}, nw);
+        if (L.bnd_elems * (int64_t)c27_record_bytes(A.dtype) >=
+            ((int64_t)1 << 31))
+            return M2S_ERR_SHAPE;
+        P.row_slots = 16;
+        P.slab_planes = L.kt;
+        P.nslabs = (int)L.tiles.size();
+        P.threads = 64 * nw;
+        P.publish_every = 1;
+        P.grid = 0;
+        if (with_grid) {
+            int dev = 0, cus = 0;
+            if (hipGetDevice(&dev) != hipSuccess) return M2S_ERR_HIP;
+            if (hipDeviceGetAttribute(&cus,
+                                      hipDeviceAttributeMultiprocessorCount,
+                                      dev) != hipSuccess)
+                return M2S_ERR_HIP;
+            // one tile per CU: a CU holds one tile's rings anyway for
+            // nw = 4, and spinning tiles should not share a CU with
+            // working ones
+            const int per_cu = std::max(1, env_int("M2S_C27_PER_CU", 1));
+            P.grid = std::max(1, std::min(P.nslabs, cus * per_cu));
+        }
+        return M2S_OK;
     } else {
         R = (nx + P.lag_row - 1) / P.lag_row;
         if (R > ny) R = ny;
@@ -165,11 +188,7 @@ m2s_status make_plan(const m2s_stencil &A, SweepPlan &P, bool with_grid)
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
                                   dev) != hipSuccess)
             return M2S_ERR_HIP;
-        int per_cu =
-            c27 ? c27_max_blocks_per_cu(
-                      A.dtype, P.threads,
-                      c27_lds_bytes(P.slab_planes, ny, A.dtype))
-                : sweep_max_blocks_per_cu(A.kind, A.dtype, P.threads);
+        int per_cu = sweep_max_blocks_per_cu(A.kind, A.dtype, P.threads);
         int64_t cap = (int64_t)cus * per_cu;
         P.grid = (int)std::min<int64_t>(P.nslabs, cap);
         if (P.grid < 1) P.grid = 1;
@@ -186,26 +205,38 @@ m2s_status check_ws(const m2s_stencil &A, const m2s_workspace *ws)
     return M2S_OK;
 }
 
-// The 27-point sweep needs one boundary buffer per slab boundary.  Grown
-// (synchronously) only when a plan with more slabs shows up.
-m2s_status ensure_boundaries(m2s_workspace *ws, int nslabs)
+// The 27-point sweep's tile table and boundary store, laid out for nw
+// wavefronts per tile; rebuilt (synchronously) when nw changes.
+m2s_status ensure_c27(m2s_workspace *ws, int nw)
 {
-    const int need = nslabs > 1 ? nslabs - 1 : 1;
-    if (ws->bnd && ws->bnd_nbuf >= need) return M2S_OK;
-    if (ws->bnd) {
+    if (ws->bnd && ws->c27_nw == nw) return M2S_OK;
+    if (ws->bnd || ws->c27_tiles) {
         if (hipDeviceSynchronize() != hipSuccess) return M2S_ERR_HIP;
-        (void)hipFree(ws->bnd);
+        if (ws->bnd) (void)hipFree(ws->bnd);
+        if (ws->c27_tiles) (void)hipFree(ws->c27_tiles);
         ws->bnd = nullptr;
+        ws->c27_tiles = nullptr;
     }
-    const int64_t n = (int64_t)need * c27_bnd_stride(ws->g.nx, ws->g.ny);
-    if (hipMalloc(&ws->bnd, n * (ws->dtype == M2S_F64 ? 8 : 4)) !=
-        hipSuccess)
+    const C27Layout L = c27_layout(ws->g, nw);
+    const int64_t n = std::max<int64_t>(L.bnd_elems, 1);
+    const size_t tb = sizeof(int2) * std::max<size_t>(L.tiles.size(), 1);
+    const size_t rb = c27_record_bytes(ws->dtype);
+    // records start with epoch 0, which no launch uses
+    if (hipMalloc(&ws->bnd, n * rb) != hipSuccess ||
+        hipMalloc(&ws->c27_tiles, tb) != hipSuccess)
         return M2S_ERR_HIP;
-    if (c27_fill_sentinel(ws->bnd, ws->dtype, n, 0) != hipSuccess ||
+    if ((!L.tiles.empty() &&
+         hipMemcpy(ws->c27_tiles, L.tiles.data(),
+                   sizeof(int2) * L.tiles.size(),
+                   hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemset(ws->bnd, 0, n * rb) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess)
         return M2S_ERR_HIP;
     ws->bnd_elems = n;
-    ws->bnd_nbuf = need;
+    ws->c27_nw = nw;
+    ws->c27_ntiles = (int)L.tiles.size();
+    ws->c27_nutb = L.nutb;
+    ws->c27_ns = L.ns;
     return M2S_OK;
 }
 
@@ -218,9 +249,10 @@ m2s_status half_sweep(const m2s_stencil &A, const Block7Consts *b7,
     SweepPlan P{};
     m2s_status st = make_plan(A, P, true);
     if (st != M2S_OK) return st;
-    if (P.nslabs > ws->nflags) return M2S_ERR_SHAPE;
+    if (A.kind != M2S_CONST27 && P.nslabs > ws->nflags)
+        return M2S_ERR_SHAPE;
     if (A.kind == M2S_CONST27 &&
-        (st = ensure_boundaries(ws, P.nslabs)) != M2S_OK)
+        (st = ensure_c27(ws, P.slab_planes / 4)) != M2S_OK)
         return st;
     return hip_status(launch_sweep(A, b7, omega, r, xin, xout, bwd, zero_init,
                                    *ws, P, s));
@@ -262,8 +294,12 @@ m2s_status m2s_plan_sweep(const m2s_stencil *A, m2s_sweep_plan *plan)
     plan->row_slots = P.row_slots;
     plan->lag_row = P.lag_row;
     plan->lag_plane = P.lag_plane;
-    plan->steps = A->ext.nx + P.lag_row * (A->ext.ny - 1) +
-                  P.lag_plane * (P.slab_planes - 1);
+    if (A->kind == M2S_CONST27)  // u = j + k: T = i + 2u + 2k
+        plan->steps = A->ext.nx + 2 * (P.row_slots - 1) +
+                      2 * (P.slab_planes - 1);
+    else
+        plan->steps = A->ext.nx + P.lag_row * (A->ext.ny - 1) +
+                      P.lag_plane * (P.slab_planes - 1);
     plan->threads = P.threads;
     plan->publish_every = P.publish_every;
     return M2S_OK;
@@ -297,7 +333,7 @@ m2s_status m2s_workspace_create(const m2s_stencil *A, m2s_workspace **out)
             m2s_workspace_destroy(ws);
             return pst;
         }
-        ok = ensure_boundaries(ws, P.nslabs) == M2S_OK;
+        ok = ensure_c27(ws, P.slab_planes / 4) == M2S_OK;
     }
     ok = ok && hipMemset(ws->flags, 0, sizeof(uint64_t) * ws->nflags) ==
                    hipSuccess &&
@@ -322,6 +358,7 @@ void m2s_workspace_destroy(m2s_workspace *ws)
     if (ws->scratch) (void)hipFree(ws->scratch);
     if (ws->scratch2) (void)hipFree(ws->scratch2);
     if (ws->bnd) (void)hipFree(ws->bnd);
+    if (ws->c27_tiles) (void)hipFree(ws->c27_tiles);
     delete ws;
 }
 
@@ -340,9 +377,6 @@ m2s_status m2s_check(m2s_workspace *ws, hipStream_t stream)
         if (hipMemcpy(&tk, ws->ticket, sizeof(tk), hipMemcpyDeviceToHost) !=
                 hipSuccess ||
             hipMemset(ws->err, 0, sizeof(int)) != hipSuccess)
-            return M2S_ERR_HIP;
-        if (ws->bnd && c27_fill_sentinel(ws->bnd, ws->dtype, ws->bnd_elems,
-                                         0) != hipSuccess)
             return M2S_ERR_HIP;
         if (hipDeviceSynchronize() != hipSuccess) return M2S_ERR_HIP;
         ws->ticket_base = tk;
@@ -741,8 +775,6 @@ m2s_status workspace_error(m2s_workspace *ws)
         uint64_t tk = 0;
         (void)hipMemcpy(&tk, ws->ticket, sizeof(tk), hipMemcpyDeviceToHost);
         (void)hipMemset(ws->err, 0, sizeof(int));
-        if (ws->bnd)
-            (void)c27_fill_sentinel(ws->bnd, ws->dtype, ws->bnd_elems, 0);
         (void)hipDeviceSynchronize();
         ws->ticket_base = tk;
         return M2S_ERR_TIMEOUT;

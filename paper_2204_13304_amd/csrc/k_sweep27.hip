@@ -1,224 +1,350 @@
 // k_sweep27.hip -- the exact lexicographic Gauss-Seidel half-sweep of the
 // 27-point operator (the HPCG SymGS of Sec. 7.1; a Seidel-style stencil,
-// Sec. 2.1.2) as a persistent wavefront kernel tuned for gfx950.
+// Sec. 2.1.2) as a persistent, tiled wavefront kernel for gfx950.
 //
-// Schedule.  A workgroup owns a slab of Bk whole planes; thread (kk, j) owns
-// row j of local plane kk and processes column i at local step
-// t = i + 2j + 4kk.  Every lower neighbour of a point has a strictly smaller
-// t (the hyperplane of Eq. (hyperplane) with weights (1,2,4), Sec. 6.1.3),
-// so one workgroup barrier per step orders all in-slab dependences.  Slabs
-// are lexicographic intervals, so dependences between slabs only point
-// forward; slabs are taken in order from a ticket counter, so a slab only
-// ever waits for one that a running workgroup owns.
+// Schedule.  Point (i, j, k) runs at global step T = i + 2j + 4k, the
+// hyperplane of Eq. (hyperplane) with weights (1, 2, 4) (Sec. 6.1.3): every
+// lower neighbour has a strictly smaller T, and no two points of one step
+// depend on each other.  Rows (j, k) are addressed by (u, k) with u = j + k,
+// so that T = i + 2u + 2k.  A tile is 16 consecutive u by KT = 4 * NW
+// consecutive k (NW wavefronts, one lane per row); the lower neighbours of
+// its rows lie in the tile itself or in tiles (u - 1, k), (u, k - 1) and
+// (u - 1, k - 1) of the tile grid, so the tile graph is acyclic (plain (j, k)
+// boxes are not: (j + 1, k - 1) is a lower neighbour of (j, k)).  Tiles are
+// handed out from a ticket counter in lexicographic (k-tile, u-tile) order,
+// so a tile only ever waits for one that a running workgroup owns.
 //
-// Data path.
-//  * "Current x" rings in LDS: for planes kk = -1 .. Bk and rows -1 .. ny a
-//    ring of 16 columns holds the newest value of x (old until the owner
-//    updates it, new afterwards) -- the in-place semantics of the paper's
-//    Seidel loop, kept only for the columns around each row's front.  Rows
-//    -1 and ny and the planes outside the grid stay zero, so the eight
-//    neighbour reads of a point need no bounds tests.  Row stride 17 keeps
-//    the skewed 64-bit reads of a wave bank-conflict free.  A thread keeps
-//    the partial column sums of columns i-1 and i in registers and reads the
-//    8 neighbour rows of column i+1 each step.
-//  * Old values and r stream from HBM through 8-slot register pipelines
-//    (slot = step mod 8, identical for every lane because all rows advance
-//    one column per step): a slot is consumed and refilled in the same step,
-//    8 steps ahead of use, with clamped always-in-bounds addresses so the
-//    loads stay in flight across steps.  Old values are staged into the rings
-//    8 columns ahead of the front.
-//  * Between slabs the top plane's new values go to a boundary buffer in
-//    diagonal layout [i + 2j][j] (i + 2j is the same for every lane at a
-//    given step, so both ends are coalesced) that starts filled with a NaN
-//    sentinel.  The next slab polls the values themselves -- the data is its
-//    own ready flag, one memory round trip, no fences -- stages them just
-//    before their first use and resets each entry to the sentinel.  Each
-//    slab boundary has its own buffer (a buffer reused within one sweep could
-//    be polled by its later consumer before the earlier one reset it).
-// The per-point arithmetic is bit-for-bit that of the sequential kernel
-// (c27_col / c27_combine association in k_sweep.hip).
+// Data path inside a tile (one workgroup barrier per step).
+//  * LDS "current x" rings, 32 columns per row, for the tile's rows plus the
+//    halo rows u0 - 2 .. u0 + 17 and planes k0 - 1 .. k0 + KT: a slot holds
+//    the old value of its column until the owner updates it and the new one
+//    afterwards -- the in-place semantics of the Seidel loop, kept only for
+//    the columns around each row's front.  Lanes of a row group sit at
+//    different columns (skew 2 per u); the padded stride 33 keeps the skewed
+//    64-bit reads bank-conflict free.
+//  * Coalesced HBM access: every 16 steps each row's next 16 columns of
+//    x_in and r are read by 16 lanes at once (4 rows per wavefront load; one
+//    group of rows per phase of the 16-step cycle), parked one cycle in
+//    registers, then written into the rings; finished 16-column pieces of
+//    x_out leave the ring the same way.  Buffer loads return 0 outside a row
+//    or the grid, which is exactly the Dirichlet padding the rings need.
+//  * A point sums the 8 neighbour rows of column i + 1 (the column sums of
+//    columns i - 1 and i stay in registers), in the association of the
+//    sequential kernel (c27_col / c27_combine in k_sweep.hip), so the two
+//    agree bit for bit.
+//  * Between tiles, the new values of the rows that neighbour tiles read
+//    (u0 + 14, u0 + 15 of every plane, u0 .. u0 + 13 of the top plane) go to
+//    a per-tile boundary store laid out by step: slice T holds every
+//    boundary row's value of step T contiguously, so producer and consumer
+//    each touch one or two cache lines per step.  Each value is written once
+//    as a record tagged with the launch's epoch; consumers poll the records
+//    themselves (one memory round trip, no fences, no resets: any number of
+//    tiles may read a record) and write the value into their rings one step
+//    before its first use.
+//  * Every memory instruction of a step is issued unconditionally (inactive
+//    lanes use an out-of-range buffer offset, which reads 0 and drops
+//    stores), so the number of instructions in flight is the same on every
+//    path and the waits the compiler places cover the whole prefetch
+//    distance.
 #include "m2s_internal.hpp"
 
 #include <algorithm>
+#include <cstdlib>
+#include <vector>
 
 namespace m2s {
 
-constexpr int C27_W = 16;     // ring columns
-constexpr int C27_WP = 17;    // padded ring stride
-constexpr int C27_LEAD = 8;   // own-ring staging lead (columns)
-constexpr int C27_U = 8;      // pipeline length = unroll (steps)
-constexpr int C27_MAX_THREADS = 512;
+constexpr int C27_TU = 16;    // u-rows per tile
+constexpr int C27_RU = 20;    // ring rows per plane: uu = -2 .. 17
+constexpr int C27_W = 32;     // x-ring columns
+constexpr int C27_WP = 33;    // padded x-ring stride
+constexpr int C27_WR = 16;    // r-ring columns
+constexpr int C27_WRP = 17;   // padded r-ring stride
+constexpr int C27_POLL = 8;   // boundary poll distance (steps)
+constexpr int C27_PRE = 48;   // steps before the smallest row skew
 
+// Raw buffer load; a byte offset at or past the end of the buffer reads 0.
 template <typename T>
-struct BitsOf;
-template <>
-struct BitsOf<double> {
-    using U = unsigned long long;
-    static constexpr U sentinel = 0x7FF4000000000BADull;
-};
-template <>
-struct BitsOf<float> {
-    using U = unsigned int;
-    static constexpr U sentinel = 0x7FA00BADu;
-};
-
-template <typename T>
-__device__ __forceinline__ T ld_relaxed(const T *p)
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t rs, unsigned off)
 {
-    using U = typename BitsOf<T>::U;
-    U v = __hip_atomic_load((const U *)p, __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT);
-    return __builtin_bit_cast(T, v);
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(
+            T, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
+    else
+        return __builtin_bit_cast(
+            T, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
 }
 
+// Boundary-store record: a value tagged with the launch epoch.  For FP64
+// the record is {lo, epoch, hi, epoch}: each 8-byte half is written and
+// read as one unit, so matching epochs in both halves mean both halves of
+// the value are from this launch.  FP32: {value, epoch}.
 template <typename T>
-__device__ __forceinline__ void st_relaxed(T *p, T v)
-{
-    using U = typename BitsOf<T>::U;
-    __hip_atomic_store((U *)p, __builtin_bit_cast(U, v), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
+struct Rec;
+template <>
+struct Rec<double> {
+    using V = __attribute__((ext_vector_type(4))) unsigned;
+    static constexpr unsigned bytes = 16;
+    __device__ static V make(double v, unsigned ep)
+    {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        return V{(unsigned)b, ep, (unsigned)(b >> 32), ep};
+    }
+    __device__ static bool ready(V r, unsigned ep)
+    {
+        return r.y == ep && r.w == ep;
+    }
+    __device__ static double value(V r)
+    {
+        return __builtin_bit_cast(
+            double, (unsigned long long)r.x | ((unsigned long long)r.z << 32));
+    }
+    __device__ static V load(__amdgpu_buffer_rsrc_t rs, unsigned off)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 16);
+    }
+    __device__ static void store(__amdgpu_buffer_rsrc_t rs, unsigned off, V r)
+    {
+        __builtin_amdgcn_raw_buffer_store_b128(r, rs, (int)off, 0, 16);
+    }
+};
+template <>
+struct Rec<float> {
+    using V = __attribute__((ext_vector_type(2))) unsigned;
+    static constexpr unsigned bytes = 8;
+    __device__ static V make(float v, unsigned ep)
+    {
+        return V{__builtin_bit_cast(unsigned, v), ep};
+    }
+    __device__ static bool ready(V r, unsigned ep) { return r.y == ep; }
+    __device__ static float value(V r)
+    {
+        return __builtin_bit_cast(float, r.x);
+    }
+    __device__ static V load(__amdgpu_buffer_rsrc_t rs, unsigned off)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 16);
+    }
+    __device__ static void store(__amdgpu_buffer_rsrc_t rs, unsigned off, V r)
+    {
+        __builtin_amdgcn_raw_buffer_store_b64(r, rs, (int)off, 0, 16);
+    }
+};
 
-template <typename T>
-__device__ __forceinline__ bool is_sentinel(T v)
+// Raw buffer store; a byte offset at or past the end of the buffer is
+// dropped.  aux 16 sets sc1: the store is made coherent at device scope,
+// like an agent-scope atomic store.
+template <typename T, int AUX>
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t rs,
+                                          unsigned off, T v)
 {
-    return __builtin_bit_cast(typename BitsOf<T>::U, v) ==
-           BitsOf<T>::sentinel;
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(
+            __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned,
+                               v),
+            rs, (int)off, 0, AUX);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(
+            __builtin_bit_cast(unsigned, v), rs, (int)off, 0, AUX);
 }
 
 template <typename T>
 struct C27Args {
     Grid g;
-    int Bk, nslabs;
+    int ntiles;          // tiles, in ticket order
+    int nutb;            // boundary-store tile slots per k-tile
+    int ns;              // boundary slices per tile
+    const int2 *tiles;   // (u-tile, k-tile) per ticket
     const T *r;
-    const T *xin;  // nullptr: start from zero
+    const T *xin;        // nullptr: start from zero
     T *xout;
     T off, inv_diag;
-    T *bnd;              // one buffer per slab boundary (nslabs - 1)
-    int64_t bnd_stride;  // (nx + 2 ny) * ny
+    void *bnd;           // boundary store (records)
+    int64_t bnd_elems;   // records
+    unsigned epoch;      // this launch's tag, never 0
     uint64_t *ticket;
     uint64_t ticket_base;
     int *err;
     int spin_limit;
 };
 
-template <typename T, bool BWD, bool ZERO>
-__global__ void __launch_bounds__(C27_MAX_THREADS)
-    c27_slab_kernel(C27Args<T> a)
+// Boundary-store slot of tile (ut, vt); the u-tiles of k-tile vt start at
+// floor(k0 / 16).
+__host__ __device__ inline int c27_slot(int ut, int vt, int KT, int nutb)
 {
+    return vt * nutb + (ut - (KT * vt) / C27_TU);
+}
+
+template <typename T, bool BWD, bool ZERO, int NW>
+__global__ void __launch_bounds__(64 * NW) c27_tile_kernel(C27Args<T> a)
+{
+    constexpr int KT = 4 * NW;           // planes per tile
+    constexpr int WB = 2 * KT + 14;      // boundary slice width (records)
+    constexpr int NRING = (KT + 2) * C27_RU;
+    constexpr int PS = C27_RU * C27_WP;  // ring plane stride
+    constexpr int RW = C27_WP;           // ring row stride
+    constexpr unsigned TS = sizeof(T);
     extern __shared__ unsigned char smem_raw[];
-    T *xc = (T *)smem_raw;
-    __shared__ int s_slab, s_abort;
+    T *const xr = (T *)smem_raw;
+    T *const rr = xr + NRING * C27_WP;
+    __shared__ int s_tile, s_abort;
 
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-    const int Bk = a.Bk;
-    const int RS = ny + 2;  // ring rows per plane (zero rows -1 and ny)
-    const int tid = threadIdx.x;
-    const int kk = tid / ny;
-    const int j = tid - kk * ny;
-    const bool lane_ok = kk < Bk;
+    const int last = (int)a.g.size() - 1;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int sub = l >> 4, cl = l & 15;
+    const int kk = 4 * w + sub;          // compute role: row (uu = cl, kk)
+    const int dir = BWD ? -1 : 1;
+    const unsigned OOB = 0x80000000u;    // reads 0
     const T zero = T(0);
     const T off = a.off, inv_diag = a.inv_diag;
-    // ring of local plane p (-1 .. Bk) and row r (-1 .. ny)
-    auto ring = [&](int p, int r) -> T * {
-        return xc + ((p + 1) * RS + (r + 1)) * C27_WP;
+    const int nbytes = (int)((unsigned)(last + 1) * TS);
+    const __amdgpu_buffer_rsrc_t rs_r =
+        __builtin_amdgcn_make_buffer_rsrc((void *)a.r, 0, nbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs_x = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(ZERO ? a.r : a.xin), 0, nbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs_o =
+        __builtin_amdgcn_make_buffer_rsrc((void *)a.xout, 0, nbytes, 0x00020000);
+    using R = Rec<T>;
+    constexpr unsigned RB = R::bytes;
+    const __amdgpu_buffer_rsrc_t rs_b = __builtin_amdgcn_make_buffer_rsrc(
+        a.bnd, 0, (int)(a.bnd_elems * RB), 0x00020000);
+    const unsigned ep = a.epoch;
+
+    auto xrow = [&](int kq, int uq) -> T * {
+        return xr + ((kq + 1) * C27_RU + (uq + 2)) * C27_WP;
     };
-    // zero the whole ring area once (rows -1 and ny stay zero for ever)
-    const int ring_elems = (Bk + 2) * RS * C27_WP;
-    for (int e = tid; e < ring_elems; e += blockDim.x) xc[e] = zero;
+    // element index of virtual column 0 of row (j, k); dir steps along it
+    auto rowbase = [&](int j, int k) -> int {
+        const int v = (k * ny + j) * nx;
+        return BWD ? last - v : v;
+    };
+    // byte offset of column c of a row; OOB outside the row or the grid
+    auto boff = [&](bool vrow, int rb, int c) -> unsigned {
+        return (vrow && (unsigned)c < (unsigned)nx)
+                   ? (unsigned)(rb + dir * c) * TS
+                   : OOB;
+    };
+
     if (tid == 0) s_abort = 0;
-    __syncthreads();
-
-    // neighbour ring rows: index (dz + 1) * 3 + (dy + 1)
-    T *const own = ring(lane_ok ? kk : 0, j);
-    T *nb[9];
-#pragma unroll
-    for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
-            nb[(dz + 1) * 3 + dy + 1] = ring(lane_ok ? kk + dz : 0, j + dy);
-
+    bool aborted = false;
     for (;;) {
+        __syncthreads();
         if (tid == 0) {
             uint64_t tk = atomicAdd((unsigned long long *)a.ticket, 1ull) -
                           a.ticket_base;
-            s_slab = tk < (uint64_t)a.nslabs ? (int)tk : -1;
+            s_tile = tk < (uint64_t)a.ntiles ? (int)tk : -1;
         }
+        for (int e = tid; e < NRING * C27_WP; e += 64 * NW) xr[e] = zero;
         __syncthreads();
-        const int slab = s_slab;
-        if (slab < 0) return;
-        const int k0 = slab * Bk;
-        const int nbp = min(Bk, nz - k0);  // planes in this slab
-        const bool has_prev = k0 > 0;
-        const bool has_next = k0 + nbp < nz;
-        const bool active = lane_ok && kk < nbp;
-        const bool is_bottom = active && kk == 0 && has_prev;
-        const bool is_top = active && kk == nbp - 1 && has_next;
-        // the ring of plane -1 must read zero on the first slab and the one
-        // above the top plane zero on the last slab (an earlier slab of this
-        // workgroup may have filled them)
-        if (!has_prev)
-            for (int e = tid; e < RS * C27_WP; e += blockDim.x) xc[e] = zero;
-        if (!has_next)
-            for (int e = tid; e < RS * C27_WP; e += blockDim.x)
-                xc[(nbp + 1) * RS * C27_WP + e] = zero;
-        T *const above = ring(nbp, j);  // plane k0 + nbp (top threads)
-        T *const below = ring(-1, j);   // plane k0 - 1 (bottom threads)
-        const T *bnd_in =
-            a.bnd + (int64_t)(slab > 0 ? slab - 1 : 0) * a.bnd_stride;
-        T *bnd_out = a.bnd + (int64_t)slab * a.bnd_stride;
-        // global rows of virtual plane kq, row j; a backward sweep walks
-        // the reflected row from its end
-        const int kv = k0 + (active ? kk : 0);
-        const int rj = BWD ? ny - 1 - j : j;
-        auto grow = [&](int kq) -> int64_t {
-            const int rk = BWD ? nz - 1 - kq : kq;
-            return ((int64_t)rk * ny + rj) * nx + (BWD ? nx - 1 : 0);
-        };
-        const int64_t row_own = grow(kv);
-        const int64_t row_up = is_top ? grow(kv + 1) : row_own;
-        const int dir = BWD ? -1 : 1;
-        // boundary entry of (column i, row j): (i + 2j) * ny + j
-        const int64_t bnd_row = 2 * (int64_t)j * ny + j;
+        const int tile = s_tile;
+        if (tile < 0 || aborted) return;
+        const int2 tv = a.tiles[tile];
+        const int ut = tv.x, vt = tv.y;
+        const int u0 = C27_TU * ut, k0 = KT * vt;
+        const int T0 = 2 * (u0 + k0);  // step of column 0 of row (u0, k0)
 
-        __syncthreads();  // ring zeroing above is complete
+        // ---- compute role: row (u0 + cl, k0 + kk) ----
+        const int uc = u0 + cl, kc = k0 + kk, jc = uc - kc;
+        const bool vc = (unsigned)jc < (unsigned)ny && kc < nz;
+        const int sc = 2 * (uc + kc);
+        T *const own = xrow(kk, cl);
+        T *const rown = rr + (kk * C27_TU + cl) * C27_WRP;
+        // boundary rows: u0 + 14, u0 + 15 of every plane (entries 0 ..
+        // 2KT - 1) and u0 .. u0 + 13 of the top plane (2KT .. 2KT + 13)
+        const int ipub = cl >= 14 ? (cl - 14) + 2 * kk
+                                  : (kk == KT - 1 ? 2 * KT + cl : -1);
+        const bool pub = vc && ipub >= 0;
+        const int bout = c27_slot(ut, vt, KT, a.nutb) * a.ns * WB;
 
-        T xo_pipe[C27_U], r_pipe[C27_U], hi_pipe[C27_U], lo_pipe[C27_U];
-#pragma unroll
-        for (int q = 0; q < C27_U; ++q) {
-            xo_pipe[q] = zero; r_pipe[q] = zero;
-            hi_pipe[q] = zero; lo_pipe[q] = zero;
+        // ---- poll role (wavefront 0, lane < 2KT + 18): a new-value halo row
+        //      and the neighbour tile / entry that publishes it ----
+        int hu = 0, hk = 0, hidx = 0, put = ut, pvt = vt;
+        if (l < 2 * KT) {  // u0 - 2, u0 - 1 of plane k0 + l / 2
+            hu = -2 + (l & 1); hk = l >> 1; hidx = l; put = ut - 1;
+        } else if (l < 2 * KT + 14) {  // plane k0 - 1, u0 .. u0 + 13
+            hu = l - 2 * KT; hk = -1; hidx = 2 * KT + hu; pvt = vt - 1;
+        } else if (l < 2 * KT + 16) {  // plane k0 - 1, u0 + 14, u0 + 15
+            hu = 14 + (l - 2 * KT - 14); hk = -1;
+            hidx = 2 * (KT - 1) + (hu - 14); pvt = vt - 1;
+        } else if (l < 2 * KT + 18) {  // plane k0 - 1, u0 - 2, u0 - 1
+            hu = -2 + (l - 2 * KT - 16); hk = -1;
+            hidx = 2 * (KT - 1) + (hu + 2); put = ut - 1; pvt = vt - 1;
         }
-        T F_m1 = zero, F_0 = zero, xn_prev = zero;
+        const int hug = u0 + hu, hkg = k0 + hk, hj = hug - hkg;
+        const bool vh = w == 0 && l < 2 * KT + 18 &&
+                        (unsigned)hj < (unsigned)ny && hkg >= 0 && hkg < nz;
+        const int sh = 2 * (hug + hkg);
+        const int T0p = 2 * (C27_TU * put + KT * pvt);
+        const int pbuf =
+            vh ? c27_slot(put, pvt, KT, a.nutb) * a.ns * WB + hidx : 0;
+        T *const hrow = xrow(vh ? hk : 0, vh ? hu : 0);
+        // record index of this lane's entry in slice T_
+        auto pslice = [&](int T_) -> int {
+            const int q = min(max(T_ - T0p, 0), a.ns - 1);
+            return pbuf + q * WB;
+        };
+
+        // ---- step range: the pipelines fill before any row's column 0,
+        //      the last rows' last pieces are stored before the end ----
+        const int T_start = T0 - 6 - C27_PRE;
+        const int T_lastc = T0 + 2 * (C27_TU - 1) + 2 * (KT - 1) + nx - 1;
+        const int nblk = (T_lastc + 2 * C27_TU + 2 - T_start + 15) / 16;
+
+        T xpipe[16], rpipe[16], hpipe[16];
+        typename R::V ppipe[C27_POLL];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) xpipe[q] = rpipe[q] = hpipe[q] = zero;
+#pragma unroll
+        for (int q = 0; q < C27_POLL; ++q) ppipe[q] = typename R::V{};
+        T Fm = zero, F0 = zero, xprev = zero;
         int spin_budget = a.spin_limit;
 
-        // own column at step t is i = t - 2j - 4kk; the loop starts early
-        // enough to fill every pipeline before column 0 is needed
-        const int t_last = (nx - 1) + 2 * (ny - 1) + 4 * (nbp - 1);
-        const int t_begin = -(C27_LEAD + C27_U + 8);
-        int col = t_begin - 2 * j - 4 * (active ? kk : 0);
-        auto clampc = [&](int c) -> int { return min(max(c, 0), nx - 1); };
-
-        bool aborted = false;
-        for (int tb = t_begin; tb <= t_last && !aborted; tb += C27_U) {
+        for (int blk = 0; blk < nblk; ++blk) {
+            const int Tb = T_start + 16 * blk;
 #pragma unroll
-            for (int tau = 0; tau < C27_U; ++tau) {
-                // ---- stage old / boundary values into the rings ----
-                // (unconditional: columns outside [0, nx) land in ring slots
-                // that are dead or never read)
-                if (active) {
-                    own[(col + C27_LEAD) & (C27_W - 1)] =
-                        ZERO ? zero : xo_pipe[tau];
-                    if (is_top)
-                        above[(col - 4 + C27_LEAD) & (C27_W - 1)] =
-                            ZERO ? zero : hi_pipe[tau];
-                    if (is_bottom) {
-                        // plane -1 column cb is first read one step later
-                        const int cb = col + 4;
-                        T v = lo_pipe[tau];
-                        if (cb >= 0 && cb < nx) {
-                            T *src = (T *)bnd_in + bnd_row + (int64_t)cb * ny;
-                            while (is_sentinel(v)) {
+            for (int ph = 0; ph < 16; ++ph) {
+                const int st = Tb + ph;
+                // ---- (1) own rows of this phase: stage x / r windows ----
+                {
+                    const int uL = 4 * (ph & 3) + sub, kL = 4 * w + (ph >> 2);
+                    const int u = u0 + uL, k = k0 + kL, j = u - k;
+                    const bool v = (unsigned)j < (unsigned)ny && k < nz;
+                    const int f = st - 2 * (u + k);
+                    const int cx = f + 8 + cl, cr = f + cl;
+                    xrow(kL, uL)[cx & (C27_W - 1)] = xpipe[ph];
+                    rr[(kL * C27_TU + uL) * C27_WRP + (cr & (C27_WR - 1))] =
+                        rpipe[ph];
+                    const int rb = v ? rowbase(j, k) : 0;
+                    if (!ZERO)
+                        xpipe[ph] = buf_load<T>(rs_x, boff(v, rb, cx + 16));
+                    rpipe[ph] = buf_load<T>(rs_r, boff(v, rb, cr + 16));
+                }
+                // ---- (2) old-value halo rows u0 + 16, u0 + 17 of the
+                //      wavefront's planes, and plane k0 + KT (top one) ----
+                if (ph < 13) {
+                    const bool lo = ph < 4;
+                    const bool mine = l < 32 && (lo || w == NW - 1);
+                    const int uH = lo ? 16 + sub : 2 * (ph - 4) + sub;
+                    const int kH = lo ? 4 * w + ph : KT;
+                    const int u = u0 + uH, k = k0 + kH, j = u - k;
+                    const bool v = mine && (unsigned)j < (unsigned)ny &&
+                                   k < nz;
+                    const int cx = st - 2 * (u + k) + 8 + cl;
+                    if (mine) xrow(kH, uH)[cx & (C27_W - 1)] = hpipe[ph];
+                    const int rb = v ? rowbase(j, k) : 0;
+                    if (!ZERO)
+                        hpipe[ph] = buf_load<T>(rs_x, boff(v, rb, cx + 16));
+                }
+                // ---- (3) new-value halo rows from the neighbour tiles ----
+                {
+                    const int c = st - sh;
+                    if (vh && c >= 0) {
+                        T v = zero;
+                        if (c < nx) {
+                            typename R::V rec = ppipe[ph & (C27_POLL - 1)];
+                            const unsigned src = (unsigned)pslice(st) * RB;
+                            while (!R::ready(rec, ep)) {
                                 if (--spin_budget < 0 ||
                                     __hip_atomic_load(
                                         a.err, __ATOMIC_RELAXED,
@@ -230,114 +356,112 @@ __global__ void __launch_bounds__(C27_MAX_THREADS)
                                     break;
                                 }
                                 __builtin_amdgcn_s_sleep(1);
-                                v = ld_relaxed(src);
+                                rec = R::load(rs_b, src);
                             }
-                            st_relaxed(src, __builtin_bit_cast(
-                                                T, BitsOf<T>::sentinel));
+                            v = R::value(rec);
                         }
-                        below[cb & (C27_W - 1)] = v;
+                        hrow[c & (C27_W - 1)] = v;
                     }
+                    // poll the slice POLL steps ahead
+                    ppipe[ph & (C27_POLL - 1)] = R::load(
+                        rs_b, vh ? (unsigned)pslice(st + C27_POLL) * RB : OOB);
                 }
-                // ---- compute the point at column col ----
-                if (active && col >= 0 && col < nx) {
-                    const int c = col + 1;
-                    const int cw = c & (C27_W - 1);
-                    // F'(c): the 8 values of column c outside the row
-                    const T v0 = nb[0][cw], v1 = nb[1][cw], v2 = nb[2][cw];
-                    const T v3 = nb[3][cw], v4 = nb[5][cw];
-                    const T v5 = nb[6][cw], v6 = nb[7][cw], v7 = nb[8][cw];
-                    const T xon_r = own[cw];
-                    const T Fp = ((v0 + v1) + (v2 + v3)) +
-                                 ((v4 + v5) + (v6 + v7));
-                    const bool in = c < nx;
-                    const T F_p1 = in ? Fp : zero;
-                    const T xon = in ? xon_r : zero;
-                    if (col == 0) {
-                        const T u0 = nb[0][0], u1 = nb[1][0], u2 = nb[2][0];
-                        const T u3 = nb[3][0], u4 = nb[5][0];
-                        const T u5 = nb[6][0], u6 = nb[7][0], u7 = nb[8][0];
-                        F_m1 = zero;
-                        F_0 = ((u0 + u1) + (u2 + u3)) + ((u4 + u5) + (u6 + u7));
-                        xn_prev = zero;
-                    }
-                    const T S = (F_m1 + F_0) + (F_p1 + xon);
-                    T tt = fma(-off, S, r_pipe[tau]);
-                    tt = fma(-off, xn_prev, tt);
-                    const T xnew = tt * inv_diag;
-                    own[col & (C27_W - 1)] = xnew;
-                    a.xout[row_own + dir * col] = xnew;
-                    if (is_top)
-                        st_relaxed(bnd_out + bnd_row + (int64_t)col * ny,
-                                   xnew);
-                    F_m1 = F_0;
-                    F_0 = F_p1;
-                    xn_prev = xnew;
-                }
-                // ---- refill the consumed pipeline slots, U steps ahead ----
+                // ---- (4) the point at column f of the own row ----
                 {
-                    if (!ZERO)
-                        xo_pipe[tau] =
-                            a.xin[row_own +
-                                  dir * clampc(col + C27_U + C27_LEAD)];
-                    r_pipe[tau] = a.r[row_own + dir * clampc(col + C27_U)];
-                    if (!ZERO)
-                        hi_pipe[tau] =
-                            a.xin[row_up +
-                                  dir * clampc(col - 4 + C27_U + C27_LEAD)];
-                    lo_pipe[tau] = ld_relaxed(
-                        bnd_in +
-                        (is_bottom ? bnd_row + (int64_t)clampc(col + 4 + C27_U) *
-                                                   ny
-                                   : 0));
+                    const int f = st - sc;
+                    const int cw = (f + 1) & (C27_W - 1);
+                    const T v0 = own[cw - PS - 2 * RW], v1 = own[cw - PS - RW];
+                    const T v2 = own[cw - PS], v3 = own[cw - RW];
+                    const T v4 = own[cw + RW], v5 = own[cw + PS];
+                    const T v6 = own[cw + PS + RW];
+                    const T v7 = own[cw + PS + 2 * RW];
+                    const T xon = own[cw];
+                    const T Fp =
+                        ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7));
+                    const T S = (Fm + F0) + (Fp + xon);
+                    T t = fma(-off, S, rown[f & (C27_WR - 1)]);
+                    t = fma(-off, xprev, t);
+                    const T x = t * inv_diag;
+                    const bool act = vc && (unsigned)f < (unsigned)nx;
+                    if (act) {
+                        own[f & (C27_W - 1)] = x;
+                        xprev = x;
+                    }
+                    R::store(rs_b,
+                             act && pub ? (unsigned)(bout + (st - T0) * WB +
+                                                     ipub) * RB
+                                        : OOB,
+                             R::make(x, ep));
+                    Fm = F0;
+                    F0 = Fp;
                 }
-                ++col;
-                __syncthreads();
+                // ---- (5) the rows staged 8 steps ago store their last 16
+                //      finished columns ----
+                {
+                    const int ps = ph ^ 8;
+                    const int uS = 4 * (ps & 3) + sub, kS = 4 * w + (ps >> 2);
+                    const int u = u0 + uS, k = k0 + kS, j = u - k;
+                    const bool v = (unsigned)j < (unsigned)ny && k < nz;
+                    const int c = st - 2 * (u + k) - 16 + cl;
+                    const T xv = xrow(kS, uS)[c & (C27_W - 1)];
+                    const int rb = v ? rowbase(j, k) : 0;
+                    buf_store<T, 0>(rs_o, boff(v, rb, c), xv);
+                }
+                if constexpr (NW > 1)
+                    __syncthreads();
+                else
+                    asm volatile("" ::: "memory");
             }
-            aborted = s_abort != 0;
+            if constexpr (NW == 1) __syncthreads();
+            if (s_abort) {
+                aborted = true;
+                break;
+            }
         }
-        if (aborted) return;
-        __syncthreads();
     }
 }
 
-// Fill boundary buffers with the sentinel pattern.
-template <typename T>
-__global__ void __launch_bounds__(256)
-    fill_sentinel_kernel(T *p, int64_t n)
+// ---------------------------------------------------------------- host --
+
+C27Layout c27_layout(Grid g, int nw)
 {
-    using U = typename BitsOf<T>::U;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-         q += (int64_t)gridDim.x * blockDim.x)
-        ((U *)p)[q] = BitsOf<T>::sentinel;
+    C27Layout L{};
+    L.nw = nw;
+    L.kt = 4 * nw;
+    L.nbands = (g.nz + L.kt - 1) / L.kt;
+    L.ns = g.nx + 2 * (C27_TU - 1) + 2 * (L.kt - 1);
+    L.wb = 2 * L.kt + 14;
+    L.nutb = 0;
+    for (int vt = 0; vt < L.nbands; ++vt) {
+        const int k0 = L.kt * vt, kmax = std::min(k0 + L.kt, g.nz) - 1;
+        const int utmin = k0 / C27_TU, utmax = (kmax + g.ny - 1) / C27_TU;
+        L.nutb = std::max(L.nutb, utmax - utmin + 1);
+        for (int ut = utmin; ut <= utmax; ++ut) {
+            // the tile holds a row (u, k) with 0 <= u - k < ny
+            const int ulo = C27_TU * ut, uhi = ulo + C27_TU - 1;
+            const int klo = std::max(k0, ulo - g.ny + 1);
+            const int khi = std::min(kmax, uhi);
+            if (klo <= khi) L.tiles.push_back(int2{ut, vt});
+        }
+    }
+    L.bnd_elems = (int64_t)L.nbands * L.nutb * L.ns * L.wb;
+    return L;
 }
 
-int c27_max_threads() { return C27_MAX_THREADS; }
-
-int64_t c27_bnd_stride(int nx, int ny) { return (int64_t)(nx + 2 * ny) * ny; }
-
-size_t c27_lds_bytes(int Bk, int ny, m2s_dtype t)
+size_t c27_lds_bytes(int nw, m2s_dtype t)
 {
-    return (size_t)(Bk + 2) * (ny + 2) * C27_WP * (t == M2S_F64 ? 8 : 4);
+    const int kt = 4 * nw;
+    const size_t es = t == M2S_F64 ? 8 : 4;
+    return ((size_t)(kt + 2) * C27_RU * C27_WP +
+            (size_t)kt * C27_TU * C27_WRP) *
+           es;
 }
 
-hipError_t c27_fill_sentinel(void *p, m2s_dtype t, int64_t n, hipStream_t s)
+template <typename T, bool BWD, bool ZERO, int NW>
+static hipError_t c27_launch_t(const C27Args<T> &a, int grid, size_t lds,
+                               hipStream_t s)
 {
-    int nb = (int)std::min<int64_t>((n + 255) / 256, 8192);
-    if (nb < 1) nb = 1;
-    if (t == M2S_F64)
-        hipLaunchKernelGGL(fill_sentinel_kernel<double>, dim3(nb), dim3(256),
-                           0, s, (double *)p, n);
-    else
-        hipLaunchKernelGGL(fill_sentinel_kernel<float>, dim3(nb), dim3(256),
-                           0, s, (float *)p, n);
-    return hipGetLastError();
-}
-
-template <typename T, bool BWD, bool ZERO>
-static hipError_t c27_launch_t(const C27Args<T> &a, int threads, int grid,
-                               size_t lds, hipStream_t s)
-{
-    auto k = c27_slab_kernel<T, BWD, ZERO>;
+    auto k = c27_tile_kernel<T, BWD, ZERO, NW>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(
@@ -346,37 +470,51 @@ static hipError_t c27_launch_t(const C27Args<T> &a, int threads, int grid,
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * NW), lds, s, a);
     return hipGetLastError();
 }
 
-int c27_max_blocks_per_cu(m2s_dtype t, int threads, size_t lds)
+template <typename T, bool BWD, bool ZERO>
+static hipError_t c27_launch_nw(const C27Args<T> &a, int nw, int grid,
+                                size_t lds, hipStream_t s)
 {
-    int n = 0;
-    hipError_t e;
-    if (t == M2S_F64)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, c27_slab_kernel<double, false, false>, threads, lds);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, c27_slab_kernel<float, false, false>, threads, lds);
-    if (e != hipSuccess || n < 1) n = 1;
-    return n;
+    switch (nw) {
+    case 1: return c27_launch_t<T, BWD, ZERO, 1>(a, grid, lds, s);
+    case 2: return c27_launch_t<T, BWD, ZERO, 2>(a, grid, lds, s);
+    case 4: return c27_launch_t<T, BWD, ZERO, 4>(a, grid, lds, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t c27_launch_dir(const C27Args<T> &a, bool bwd, bool zero,
+                                 int nw, int grid, size_t lds, hipStream_t s)
+{
+    if (bwd)
+        return zero ? c27_launch_nw<T, true, true>(a, nw, grid, lds, s)
+                    : c27_launch_nw<T, true, false>(a, nw, grid, lds, s);
+    return zero ? c27_launch_nw<T, false, true>(a, nw, grid, lds, s)
+                : c27_launch_nw<T, false, false>(a, nw, grid, lds, s);
 }
 
 hipError_t launch_sweep27(const m2s_stencil &A, const void *r,
                           const void *xin, void *xout, bool bwd,
                           Workspace &ws, const SweepPlan &plan, hipStream_t s)
 {
-    const size_t lds = c27_lds_bytes(plan.slab_planes, A.ext.ny, A.dtype);
-    // this launch takes tickets [base, base + nslabs + grid)
+    const int nw = plan.slab_planes / 4;
+    const size_t lds = c27_lds_bytes(nw, A.dtype);
+    // this launch takes tickets [base, base + ntiles + grid)
     const uint64_t base = ws.ticket_base;
     ws.ticket_base += (uint64_t)plan.nslabs + (uint64_t)plan.grid;
+    // boundary records of earlier launches carry other epochs
+    if (++ws.epoch == 0) ++ws.epoch;
+    const unsigned epoch = ws.epoch;
     auto fill = [&](auto &a) {
         a.g = Grid{A.ext.nx, A.ext.ny, A.ext.nz};
-        a.Bk = plan.slab_planes;
-        a.nslabs = plan.nslabs;
-        a.bnd_stride = c27_bnd_stride(A.ext.nx, A.ext.ny);
+        a.ntiles = plan.nslabs;
+        a.nutb = ws.c27_nutb;
+        a.ns = ws.c27_ns;
+        a.tiles = ws.c27_tiles;
         a.ticket = ws.ticket;
         a.ticket_base = base;
         a.err = ws.err;
@@ -392,16 +530,10 @@ hipError_t launch_sweep27(const m2s_stencil &A, const void *r,
         a.xout = (double *)xout;
         a.off = A.offdiag;
         a.inv_diag = 1.0 / A.diag;
-        a.bnd = (double *)ws.bnd;
-        if (bwd)
-            return zero ? c27_launch_t<double, true, true>(a, plan.threads,
-                                                           plan.grid, lds, s)
-                        : c27_launch_t<double, true, false>(a, plan.threads,
-                                                            plan.grid, lds, s);
-        return zero ? c27_launch_t<double, false, true>(a, plan.threads,
-                                                        plan.grid, lds, s)
-                    : c27_launch_t<double, false, false>(a, plan.threads,
-                                                         plan.grid, lds, s);
+        a.bnd = ws.bnd;
+        a.bnd_elems = ws.bnd_elems;
+        a.epoch = epoch;
+        return c27_launch_dir(a, bwd, zero, nw, plan.grid, lds, s);
     }
     C27Args<float> a{};
     fill(a);
@@ -410,16 +542,10 @@ hipError_t launch_sweep27(const m2s_stencil &A, const void *r,
     a.xout = (float *)xout;
     a.off = (float)A.offdiag;
     a.inv_diag = (float)(1.0 / A.diag);
-    a.bnd = (float *)ws.bnd;
-    if (bwd)
-        return zero ? c27_launch_t<float, true, true>(a, plan.threads,
-                                                      plan.grid, lds, s)
-                    : c27_launch_t<float, true, false>(a, plan.threads,
-                                                       plan.grid, lds, s);
-    return zero ? c27_launch_t<float, false, true>(a, plan.threads, plan.grid,
-                                                   lds, s)
-                : c27_launch_t<float, false, false>(a, plan.threads, plan.grid,
-                                                    lds, s);
+    a.bnd = ws.bnd;
+    a.bnd_elems = ws.bnd_elems;
+    a.epoch = epoch;
+    return c27_launch_dir(a, bwd, zero, nw, plan.grid, lds, s);
 }
 
 }  // namespace m2s

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <vector>
 
 #include "../../include/m2s.h"
 
@@ -94,9 +95,13 @@ struct Workspace {
     int *err;           // device error latch
     void *scratch;      // one vector of the stencil's size
     void *scratch2;     // second vector (adjoint chains)
-    void *bnd;          // 27-point sweep: per-boundary buffers (NaN-boxed)
-    int64_t bnd_elems;
-    int bnd_nbuf;       // boundary buffers allocated
+    void *bnd;          // 27-point sweep: tile boundary store (records)
+    int64_t bnd_elems;  // records
+    int c27_nw;         // wavefronts per tile the store was laid out for
+    int c27_ntiles;
+    int c27_nutb;       // boundary-store tile slots per k-tile
+    int c27_ns;         // boundary slices per tile
+    int2 *c27_tiles;    // (u-tile, k-tile) per ticket, device
     int64_t nflags;
     uint32_t epoch;
     uint64_t ticket_base;
@@ -145,11 +150,16 @@ hipError_t launch_sweep27(const m2s_stencil &A, const void *r,
                           const void *xin, void *xout, bool bwd,
                           Workspace &ws, const SweepPlan &plan,
                           hipStream_t s);
-int c27_max_threads();
-int64_t c27_bnd_stride(int nx, int ny);
-size_t c27_lds_bytes(int Bk, int R, m2s_dtype t);
-hipError_t c27_fill_sentinel(void *p, m2s_dtype t, int64_t n, hipStream_t s);
-int c27_max_blocks_per_cu(m2s_dtype t, int threads, size_t lds);
+// Tiling of the 27-point sweep: tiles of 16 u = j + k by 4 * nw planes.
+struct C27Layout {
+    int nw, kt, nbands, nutb, ns, wb;
+    int64_t bnd_elems;
+    std::vector<int2> tiles;  // valid tiles in ticket order
+};
+C27Layout c27_layout(Grid g, int nw);
+size_t c27_lds_bytes(int nw, m2s_dtype t);
+// bytes of one boundary record: the value and the launch epoch
+inline size_t c27_record_bytes(m2s_dtype t) { return t == M2S_F64 ? 16 : 8; }
 
 // CG vector kernels (double).  Scalars live in a small device array `sc`.
 enum CgScalar {

@@ -43,7 +43,10 @@ def test_plan_validation_errors():
     assert lib.m2s_plan_sweep(None, C.byref(p)) == 1
     assert lib.m2s_plan_sweep(C.byref(s), C.byref(p)) == 0
     assert p.lag_row == 2 and p.lag_plane == 4
-    s.ext = L.Extent(64, 2048, 4)  # more rows than a workgroup holds
+    s.ext = L.Extent(64, 2048, 4)
+    assert lib.m2s_plan_sweep(C.byref(s), C.byref(p)) == 0
+    # the tiled 27-point sweep addresses a vector with 32-bit byte offsets
+    s.ext = L.Extent(1024, 1024, 256)
     assert lib.m2s_plan_sweep(C.byref(s), C.byref(p)) == 2
 
 
@@ -51,8 +54,24 @@ def test_plan_validation_errors():
 def test_plan_shapes(n):
     import paper_2204_13304_amd as m
     p = m.plan_sweep(m.const27((n, n, n)))
-    # 27 points: one thread per row of a plane
-    assert p["row_slots"] == n
-    assert p["threads"] % 64 == 0 and p["threads"] <= 1024
-    assert p["slab_planes"] * p["row_slots"] <= p["threads"]
-    assert p["nslabs"] * p["slab_planes"] >= n
+    # 27 points: tiles of 16 rows u = j + k by 4 planes per wavefront,
+    # one lane per row
+    assert p["row_slots"] == 16
+    assert p["slab_planes"] % 4 == 0
+    assert p["threads"] == 16 * p["slab_planes"]
+    assert p["nslabs"] == len(c27_tiles((n, n, n), p["slab_planes"]))
+
+
+def c27_tiles(shape, kt):
+    """(u-tile, k-tile) pairs holding a grid row (j = u - k), in
+    lexicographic (k-tile, u-tile) order."""
+    nz, ny, nx = shape
+    out = []
+    for vt in range(-(-nz // kt)):
+        for ut in range(0, (ny + nz) // 16 + 2):
+            rows = [(u, k) for u in range(16 * ut, 16 * ut + 16)
+                    for k in range(kt * vt, min(kt * vt + kt, nz))
+                    if 0 <= u - k < ny]
+            if rows:
+                out.append((ut, vt))
+    return out

@@ -94,19 +94,16 @@ def model_schedule(shape, plan, c27):
 
 
 @pytest.mark.parametrize("kind,shape", [
-    ("c27", (9, 7, 6)), ("c27", (5, 3, 11)), ("c27", (16, 16, 16)),
-    ("c27", (13, 26, 9)), ("v7", (9, 7, 6)), ("v7", (6, 5, 12)),
-    ("b7", (7, 4, 5)),
+    ("v7", (9, 7, 6)), ("v7", (6, 5, 12)), ("b7", (7, 4, 5)),
 ])
 @pytest.mark.parametrize("bk", [1, 2, 3, 0])
 def test_gpu_schedule_satisfies_all_dependences(kind, shape, bk, monkeypatch):
+    """Slab schedule of the 7-point sweeps (VAR7, BLOCK7)."""
     import paper_2204_13304_amd as m
     if bk:
         monkeypatch.setenv("M2S_SLAB_PLANES", str(bk))
     nz, ny, nx = shape
-    if kind == "c27":
-        A = m.const27(shape)
-    elif kind == "v7":
+    if kind == "v7":
         import torch
         A = m.Stencil.__new__(m.Stencil)
         A.kind, A.shape, A.dtype = 1, shape, torch.float64
@@ -114,7 +111,6 @@ def test_gpu_schedule_satisfies_all_dependences(kind, shape, bk, monkeypatch):
         A.blocks = None
         # faces are only read by the kernels; planning needs non-null
         # pointers, so fake addresses are enough for this host-only call
-        import ctypes as C
         from paper_2204_13304_amd import _lib as L
         s = L.StencilC()
         s.kind, s.dtype = 1, 0
@@ -124,9 +120,8 @@ def test_gpu_schedule_satisfies_all_dependences(kind, shape, bk, monkeypatch):
     else:
         A = m.block7(shape, np.eye(5)[None].repeat(7, 0) * 10)
     plan = m.plan_sweep(A)
-    c27 = kind == "c27"
-    step, slab, D, G, Tfull = model_schedule(shape, plan, c27)
-    offs = lower_offsets_27() if c27 else lower_offsets_7()
+    step, slab, D, G, Tfull = model_schedule(shape, plan, False)
+    offs = lower_offsets_7()
     for k in range(nz):
         for j in range(ny):
             for i in range(nx):
@@ -139,17 +134,6 @@ def test_gpu_schedule_satisfies_all_dependences(kind, shape, bk, monkeypatch):
                     ta, Ka = step[a], slab[a]
                     if Ka == K:
                         assert ta < t, (a, (k, j, i))
-                    elif c27:
-                        # the 27-point kernel hands the previous slab's top
-                        # plane over value by value: row j' of plane k0-1 is
-                        # staged at column i' one step before its first read
-                        # (at local step i' + 2j' - 3, by row j'-1) and the
-                        # stage waits until the value has been written
-                        assert Ka == K - 1
-                        _, jp, ip = a
-                        stage_step = ip - 4 + 2 * jp
-                        first_read = ip + 2 * jp - 3
-                        assert stage_step < first_read <= t
                     else:
                         # producer slab must be exactly the previous one and
                         # covered by the progress wait of the G-window
@@ -157,3 +141,227 @@ def test_gpu_schedule_satisfies_all_dependences(kind, shape, bk, monkeypatch):
                         t0 = t - t % G
                         need = min(Tfull, t0 + G - 1 + D)
                         assert ta < need, (a, (k, j, i), ta, need)
+
+
+# ---------------------------------------------------------------------------
+# Model of the tiled 27-point sweep kernel.  It replays the kernel's index
+# arithmetic (tiles of 16 u = j + k by KT planes, LDS rings of 32 x columns
+# and 16 r columns, the five per-step roles of every lane) on symbolic
+# values and checks every read: lower neighbours must hold the new value,
+# upper ones the old value, anything outside the grid zero; no slot may be
+# written by one wavefront and touched by another in the same step; and
+# every point must be stored exactly once, with its new value.
+# ---------------------------------------------------------------------------
+TU, RU, W, WR, POLL, PRE = 16, 20, 32, 16, 8, 48
+
+
+def c27_tile_list(shape, kt):
+    nz, ny, nx = shape
+    out = []
+    for vt in range(-(-nz // kt)):
+        k0, kmax = kt * vt, min(kt * vt + kt, nz) - 1
+        for ut in range(k0 // TU, (kmax + ny - 1) // TU + 1):
+            ulo, uhi = TU * ut, TU * ut + TU - 1
+            if max(k0, ulo - ny + 1) <= min(kmax, uhi):
+                out.append((ut, vt))
+    return out
+
+
+def simulate_c27_tiles(shape, nw, zero_start=False):
+    nz, ny, nx = shape
+    KT = 4 * nw
+    tiles = c27_tile_list(shape, KT)
+    ticket = {t: n for n, t in enumerate(tiles)}
+    stored = {}
+
+    def valid(u, k):
+        return 0 <= u - k < ny and 0 <= k < nz
+
+    def old(u, k, c):
+        if not valid(u, k) or not 0 <= c < nx or zero_start:
+            return 0
+        return ("old", u - k, k, c)
+
+    for (ut, vt) in tiles:
+        u0, k0 = TU * ut, KT * vt
+        T0 = 2 * (u0 + k0)
+        xr, rr = {}, {}          # slot -> (value, step, wave)
+        T_start = T0 - 6 - PRE
+        T_lastc = T0 + 2 * (TU - 1) + 2 * (KT - 1) + nx - 1
+        nblk = (T_lastc + 2 * TU + 2 - T_start + 15) // 16
+        F = {}                   # lane -> [Fm, F0] column tags
+        for blk in range(nblk):
+            for ph in range(16):
+                T = T_start + 16 * blk + ph
+                writes = []      # (ring, slot, value, wave, role)
+                reads = []       # (ring, slot, wave, role, expected)
+
+                def xslot(kq, uq, c):
+                    return ((kq + 1) * RU + (uq + 2), c % W)
+
+                for w in range(nw):
+                    for lane in range(64):
+                        sub, cl = lane >> 4, lane & 15
+                        # (1) own rows of this phase
+                        uL, kL = 4 * (ph & 3) + sub, 4 * w + (ph >> 2)
+                        u, k = u0 + uL, k0 + kL
+                        f = T - 2 * (u + k)
+                        cx, cr = f + 8 + cl, f + cl
+                        # value loaded one cycle ago for the same column
+                        vx = 0 if T - 16 < T_start else old(u, k, cx)
+                        writes.append(("x", xslot(kL, uL, cx), vx, w, 1))
+                        vr = (0 if T - 16 < T_start or not valid(u, k) or
+                              not 0 <= cr < nx else ("r", u - k, k, cr))
+                        writes.append(("r", ((kL * TU + uL), cr % WR), vr,
+                                       w, 1))
+                        # (2) old-value halo rows
+                        if lane < 32 and (ph < 4 or (w == nw - 1 and
+                                                     ph < 13)):
+                            lo = ph < 4
+                            uH = 16 + sub if lo else 2 * (ph - 4) + sub
+                            kH = 4 * w + ph if lo else KT
+                            cxh = T - 2 * (u0 + uH + k0 + kH) + 8 + cl
+                            vh = (0 if T - 16 < T_start else
+                                  old(u0 + uH, k0 + kH, cxh))
+                            writes.append(("x", xslot(kH, uH, cxh), vh, w, 2))
+                        # (3) new-value halo rows (wavefront 0)
+                        if w == 0 and lane < 2 * KT + 18:
+                            if lane < 2 * KT:
+                                hu, hk = -2 + (lane & 1), lane >> 1
+                                prod, hidx = (ut - 1, vt), lane
+                            elif lane < 2 * KT + 14:
+                                hu, hk = lane - 2 * KT, -1
+                                prod, hidx = (ut, vt - 1), 2 * KT + hu
+                            elif lane < 2 * KT + 16:
+                                hu, hk = 14 + lane - 2 * KT - 14, -1
+                                prod = (ut, vt - 1)
+                                hidx = 2 * (KT - 1) + hu - 14
+                            else:
+                                hu, hk = -2 + lane - 2 * KT - 16, -1
+                                prod = (ut - 1, vt - 1)
+                                hidx = 2 * (KT - 1) + hu + 2
+                            hug, hkg = u0 + hu, k0 + hk
+                            c = T - 2 * (hug + hkg)
+                            if valid(hug, hkg) and c >= 0:
+                                if c < nx:
+                                    assert prod in ticket and \
+                                        ticket[prod] < ticket[(ut, vt)]
+                                    # the producer publishes this row at
+                                    # entry hidx of its slice
+                                    uup = hug - TU * prod[0]
+                                    kkp = hkg - KT * prod[1]
+                                    assert 0 <= uup < TU and 0 <= kkp < KT
+                                    ent = ((uup - 14) + 2 * kkp if uup >= 14
+                                           else (2 * KT + uup
+                                                 if kkp == KT - 1 else -1))
+                                    assert ent == hidx, (ent, hidx)
+                                    v = ("new", hug - hkg, hkg, c)
+                                else:
+                                    v = 0
+                                writes.append(("x", xslot(hk, hu, c), v, w,
+                                               3))
+                        # (4) compute
+                        kk = 4 * w + sub
+                        u, k = u0 + cl, k0 + kk
+                        f = T - 2 * (u + k)
+                        c = f + 1
+                        nbrs = [(-2, -1), (-1, -1), (0, -1), (-1, 0),
+                                (1, 0), (0, 1), (1, 1), (2, 1)]
+                        exp = []
+                        for du, dk in nbrs:
+                            ua, ka = u + du, k + dk
+                            lower = dk < 0 or (dk == 0 and du < 0)
+                            if not valid(ua, ka) or not 0 <= c < nx:
+                                e = 0
+                            elif lower:
+                                e = ("new", ua - ka, ka, c)
+                            else:
+                                e = old(ua, ka, c)
+                            reads.append(("x", xslot(kk + dk, cl + du, c), w,
+                                          4, e))
+                        if valid(u, k) and -2 <= f < nx:
+                            reads.append(("x", xslot(kk, cl, c), w, 4,
+                                          old(u, k, c) if c < nx else 0))
+                        if valid(u, k) and 0 <= f < nx:
+                            reads.append(("r", ((kk * TU + cl), f % WR), w,
+                                          4, ("r", u - k, k, f)))
+                            writes.append(("x", xslot(kk, cl, f),
+                                           ("new", u - k, k, f), w, 4))
+                        # (5) stores of the rows staged 8 steps ago
+                        ps = ph ^ 8
+                        uS, kS = 4 * (ps & 3) + sub, 4 * w + (ps >> 2)
+                        u, k = u0 + uS, k0 + kS
+                        c = T - 2 * (u + k) - 16 + cl
+                        if valid(u, k) and 0 <= c < nx:
+                            reads.append(("x", xslot(kS, uS, c), w, 5,
+                                          ("new", u - k, k, c)))
+                            key = (k, u - k, c)
+                            assert key not in stored, key
+                            stored[key] = True
+                # same-step hazards between wavefronts
+                wsl = {}
+                for ring, slot, v, w, role in writes:
+                    prev = wsl.get((ring, slot))
+                    if prev is not None:
+                        assert prev[1] == w, ("write race", ring, slot, T)
+                    wsl[(ring, slot)] = (v, w, role)
+                for ring, slot, w, role, e in reads:
+                    wr = wsl.get((ring, slot))
+                    mem = xr if ring == "x" else rr
+                    if wr is not None:
+                        assert wr[1] == w, ("read/write race", ring, slot, T)
+                        got = wr[0] if wr[2] < role else mem.get(slot, 0)
+                    else:
+                        got = mem.get(slot, 0)
+                    if role == 4 and e is not None:
+                        pass
+                    assert got == e, (T, ring, slot, role, got, e)
+                for (ring, slot), (v, w, role) in wsl.items():
+                    (xr if ring == "x" else rr)[slot] = v
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                assert (k, j, i) in stored, ("not stored", (k, j, i))
+
+
+@pytest.mark.parametrize("shape", [(9, 7, 6), (5, 3, 11), (6, 20, 37),
+                                   (13, 5, 4), (17, 18, 3), (1, 1, 1)])
+@pytest.mark.parametrize("nw", [1, 2, 4])
+def test_c27_tile_model(shape, nw):
+    simulate_c27_tiles(shape, nw)
+
+
+def test_c27_tile_model_zero_start():
+    simulate_c27_tiles((6, 9, 5), 2, zero_start=True)
+
+
+def test_c27_tile_dependences_point_to_earlier_tiles():
+    # every lower neighbour lies in the same tile or in tile (u-1, k),
+    # (u, k-1) or (u-1, k-1), each with an earlier ticket
+    for shape, kt in (((9, 7, 6), 4), ((23, 40, 5), 8), ((16, 16, 16), 16)):
+        nz, ny, nx = shape
+        tiles = c27_tile_list(shape, kt)
+        ticket = {t: n for n, t in enumerate(tiles)}
+        for k in range(nz):
+            for j in range(ny):
+                u = j + k
+                tp = (u // TU, k // kt)
+                assert tp in ticket
+                for dk, dj, di in lower_offsets_27():
+                    ka, ja = k - dk, j - dj
+                    if not (0 <= ka < nz and 0 <= ja < ny):
+                        continue
+                    ta = ((ja + ka) // TU, ka // kt)
+                    assert ta in (tp, (tp[0] - 1, tp[1]), (tp[0], tp[1] - 1),
+                                  (tp[0] - 1, tp[1] - 1))
+                    assert ticket[ta] <= ticket[tp]
+
+
+@pytest.mark.parametrize("shape", [(9, 7, 6), (16, 16, 16), (13, 26, 9)])
+def test_c27_plan_matches_tile_model(shape, monkeypatch):
+    import paper_2204_13304_amd as m
+    for nw in (1, 2, 4):
+        monkeypatch.setenv("M2S_C27_WAVES", str(nw))
+        p = m.plan_sweep(m.const27(shape))
+        assert p["slab_planes"] == 4 * nw and p["threads"] == 64 * nw
+        assert p["nslabs"] == len(c27_tile_list(shape, 4 * nw))
