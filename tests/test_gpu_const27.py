@@ -51,13 +51,13 @@ def test_symgs_parity_and_bitwise(m, shape, direction):
     assert np.array_equal(out, host(xs)), "wavefront != sequential"
 
 
-@pytest.mark.parametrize("bk", ["1", "2", "3", "8"])
-def test_symgs_slab_thickness_bitwise(m, bk, monkeypatch):
-    # every slab thickness gives the identical result (only the schedule
-    # changes, never the arithmetic)
-    monkeypatch.setenv("M2S_SLAB_PLANES", bk)
+@pytest.mark.parametrize("nw", ["1", "2", "4"])
+def test_symgs_tile_height_bitwise(m, nw, monkeypatch):
+    # every tile height (4 planes per wavefront, 1, 2 or 4 wavefronts) gives
+    # the identical result: only the schedule changes, never the arithmetic
+    monkeypatch.setenv("M2S_C27_WAVES", nw)
     shape = (21, 19, 23)
-    banner(f"symgs27 slab planes {bk}")
+    banner(f"symgs27 wavefronts per tile {nw}")
     A = m.const27(shape)
     r = inputs.standard_normal(3, shape)
     x0 = inputs.standard_normal(4, shape)
