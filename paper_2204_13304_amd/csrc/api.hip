@@ -133,10 +133,11 @@ m2s_status make_plan(const m2s_stencil &A, SweepPlan &P, bool with_grid)
         // buffer loads address a vector with 32-bit byte offsets
         if ((int64_t)nx * ny * nz * elem_size(A) >= ((int64_t)1 << 31))
             return M2S_ERR_SHAPE;
-        // 4 wavefronts (16 planes) per tile: fewest tile crossings along
-        // the k chain; small grids gain nothing from smaller tiles
-        int nw = env_int("M2S_C27_WAVES", 4);
-        if (nw != 1 && nw != 2 && nw != 4) nw = 4;
+        // 2 compute wavefronts (8 planes) per tile: with the memory and poll
+        // wavefronts that is 5 per CU; 4 compute wavefronts halve the tile
+        // crossings along k but put 3 wavefronts on a SIMD
+        int nw = env_int("M2S_C27_WAVES", 2);
+        if (nw != 1 && nw != 2 && nw != 4) nw = 2;
         const C27Layout L = c27_layout(Grid{nx, ny, nz}, nw);
         if (L.bnd_elems * (int64_t)c27_record_bytes(A.dtype) >=
             ((int64_t)1 << 31))
@@ -144,7 +145,7 @@ m2s_status make_plan(const m2s_stencil &A, SweepPlan &P, bool with_grid)
         P.row_slots = 16;
         P.slab_planes = L.kt;
         P.nslabs = (int)L.tiles.size();
-        P.threads = 64 * nw;
+        P.threads = c27_threads(nw);
         P.publish_every = 1;
         P.grid = 0;
         if (with_grid) {

@@ -44,14 +44,23 @@ __device__ __forceinline__ T ld(const T *a, int64_t q)
     return a ? a[q] : T(0);
 }
 
-// CONST27 partial column sum F'(c) for the row (j,k): the 8 values of
-// column c outside the row itself, in a fixed pairing order.
+// CONST27 column sums for the row (j, k).  The 8 values of column c outside
+// the row: v0 (j-1,k-1), v1 (j,k-1), v2 (j+1,k-1), v3 (j-1,k), v4 (j+1,k),
+// v5 (j-1,k+1), v6 (j,k+1), v7 (j+1,k+1), zero outside the grid.  In a
+// forward sweep v2 and v3 of column i + 1 are the values updated just
+// before point i (the tiled kernel reads them last), so the sum is split
+// into A(c) = ((v0 + v1) + (v4 + v5)) + (v6 + v7) and D(c) = v2 + v3, and
+// F(c) = A(c) + D(c).
 template <typename T, bool BWD>
-__device__ __forceinline__ T c27_col(const Virt<BWD> &V, const T *xn,
-                                     const T *xo, int c, int j, int k)
+__device__ __forceinline__ void c27_col(const Virt<BWD> &V, const T *xn,
+                                        const T *xo, int c, int j, int k,
+                                        T &A, T &D)
 {
     const Grid &g = V.g;
-    if (c < 0 || c >= g.nx) return T(0);
+    if (c < 0 || c >= g.nx) {
+        A = D = T(0);
+        return;
+    }
     const bool jm = j > 0, jp = j < g.ny - 1, km = k > 0, kp = k < g.nz - 1;
     T v0 = (km && jm) ? xn[V.idx(c, j - 1, k - 1)] : T(0);
     T v1 = km ? xn[V.idx(c, j, k - 1)] : T(0);
@@ -61,20 +70,8 @@ __device__ __forceinline__ T c27_col(const Virt<BWD> &V, const T *xn,
     T v5 = (kp && jm) ? ld(xo, V.idx(c, j - 1, k + 1)) : T(0);
     T v6 = kp ? ld(xo, V.idx(c, j, k + 1)) : T(0);
     T v7 = (kp && jp) ? ld(xo, V.idx(c, j + 1, k + 1)) : T(0);
-    return ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7));
-}
-
-// x_p = (r_p - off * S - off * x_{i-1}) / diag with
-// S = (F'(i-1) + F'(i)) + (F'(i+1) + x_old(i+1)); the division is a
-// multiplication by the precomputed reciprocal.
-template <typename T>
-__device__ __forceinline__ T c27_combine(T r, T fm, T f0, T fp, T xo_next,
-                                         T xn_prev, T off, T inv_diag)
-{
-    T S = (fm + f0) + (fp + xo_next);
-    T t = fma(-off, S, r);
-    t = fma(-off, xn_prev, t);
-    return t * inv_diag;
+    A = ((v0 + v1) + (v4 + v5)) + (v6 + v7);
+    D = v2 + v3;
 }
 
 template <typename T, bool BWD>
@@ -83,13 +80,14 @@ __device__ __forceinline__ T c27_point(const Virt<BWD> &V, const T *r,
                                        int k, T off, T inv_diag)
 {
     const Grid &g = V.g;
-    T fm = c27_col<T, BWD>(V, xn, xo, i - 1, j, k);
-    T f0 = c27_col<T, BWD>(V, xn, xo, i, j, k);
-    T fp = c27_col<T, BWD>(V, xn, xo, i + 1, j, k);
-    T xon = (i < g.nx - 1) ? ld(xo, V.idx(i + 1, j, k)) : T(0);
-    T xnp = (i > 0) ? xn[V.idx(i - 1, j, k)] : T(0);
-    return c27_combine(r[V.idx(i, j, k)], fm, f0, fp, xon, xnp, off,
-                       inv_diag);
+    T Am, Dm, A0, D0, Ap, Dp;
+    c27_col<T, BWD>(V, xn, xo, i - 1, j, k, Am, Dm);
+    c27_col<T, BWD>(V, xn, xo, i, j, k, A0, D0);
+    c27_col<T, BWD>(V, xn, xo, i + 1, j, k, Ap, Dp);
+    const T xon = (i < g.nx - 1) ? ld(xo, V.idx(i + 1, j, k)) : T(0);
+    const T xnp = (i > 0) ? xn[V.idx(i - 1, j, k)] : T(0);
+    const T B = ((Am + Dm) + (A0 + D0)) + (Ap + xon);
+    return c27_combine(r[V.idx(i, j, k)], B, Dp, xnp, off, inv_diag);
 }
 
 // VAR7: x_p = (r_p + sum_d k_d x_q) / (sum_d k_d), real directions in the

@@ -28,10 +28,12 @@
 //    registers, then written into the rings; finished 16-column pieces of
 //    x_out leave the ring the same way.  Buffer loads return 0 outside a row
 //    or the grid, which is exactly the Dirichlet padding the rings need.
-//  * A point sums the 8 neighbour rows of column i + 1 (the column sums of
-//    columns i - 1 and i stay in registers), in the association of the
-//    sequential kernel (c27_col / c27_combine in k_sweep.hip), so the two
-//    agree bit for bit.
+//  * A point needs the 8 neighbour rows of column i + 1.  Six of them and
+//    the row's own old value are read one step early (with the column sum
+//    of column i and the combination B of the point); only v2 + v3, the two
+//    values written in the previous step, are read on the critical path.
+//    The association is that of the sequential kernel (c27_col in
+//    k_sweep.hip, c27_combine), so the two agree bit for bit.
 //  * Between tiles, the new values of the rows that neighbour tiles read
 //    (u0 + 14, u0 + 15 of every plane, u0 .. u0 + 13 of the top plane) go to
 //    a per-tile boundary store laid out by step: slice T holds every
@@ -60,8 +62,12 @@ constexpr int C27_W = 32;     // x-ring columns
 constexpr int C27_WP = 33;    // padded x-ring stride
 constexpr int C27_WR = 16;    // r-ring columns
 constexpr int C27_WRP = 17;   // padded r-ring stride
-constexpr int C27_POLL = 8;   // boundary poll distance (steps)
-constexpr int C27_PRE = 48;   // steps before the smallest row skew
+// Boundary poll distance (steps).  A consumer tile settles at a lag of
+// about POLL steps plus one device-scope round trip behind its neighbour, and
+// every tile crossing on the critical path pays that lag; 4 steps already
+// cover the round trip of a poll at the compute wavefronts' step rate.
+constexpr int C27_POLL = 4;
+constexpr int C27_PRE = 18;   // steps before the smallest row skew
 
 // Raw buffer load; a byte offset at or past the end of the buffer reads 0.
 template <typename T>
@@ -175,14 +181,24 @@ __host__ __device__ inline int c27_slot(int ut, int vt, int KT, int nutb)
     return vt * nutb + (ut - (KT * vt) / C27_TU);
 }
 
+// Wavefront roles.  NW compute wavefronts (one lane per row: LDS rings and
+// FP64 only, plus the device-scope boundary publication, which nothing waits
+// on); NW memory wavefronts (memory wavefront m stages the old values and r
+// of compute wavefront m's rows and stores its finished pieces); one poll
+// wavefront (the boundary records of the neighbour tiles).  Each role runs
+// its own step loop with the same number of barriers, so every wavefront
+// waits only for its own memory instructions.  A value written in step T by
+// one wavefront is first read in step T + 1 by another.
 template <typename T, bool BWD, bool ZERO, int NW>
-__global__ void __launch_bounds__(64 * NW) c27_tile_kernel(C27Args<T> a)
+__global__ void __launch_bounds__(64 * (2 * NW + 1))
+    c27_tile_kernel(C27Args<T> a)
 {
     constexpr int KT = 4 * NW;           // planes per tile
     constexpr int WB = 2 * KT + 14;      // boundary slice width (records)
     constexpr int NRING = (KT + 2) * C27_RU;
     constexpr int PS = C27_RU * C27_WP;  // ring plane stride
     constexpr int RW = C27_WP;           // ring row stride
+    constexpr int NT = 64 * (2 * NW + 1);
     constexpr unsigned TS = sizeof(T);
     extern __shared__ unsigned char smem_raw[];
     T *const xr = (T *)smem_raw;
@@ -191,28 +207,22 @@ __global__ void __launch_bounds__(64 * NW) c27_tile_kernel(C27Args<T> a)
 
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const int last = (int)a.g.size() - 1;
-    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
     const int sub = l >> 4, cl = l & 15;
-    const int kk = 4 * w + sub;          // compute role: row (uu = cl, kk)
     const int dir = BWD ? -1 : 1;
-    const unsigned OOB = 0x80000000u;    // reads 0
+    const unsigned OOB = 0x80000000u;    // reads 0, drops stores
     const T zero = T(0);
     const T off = a.off, inv_diag = a.inv_diag;
     const int nbytes = (int)((unsigned)(last + 1) * TS);
-    const __amdgpu_buffer_rsrc_t rs_r =
-        __builtin_amdgcn_make_buffer_rsrc((void *)a.r, 0, nbytes, 0x00020000);
-    const __amdgpu_buffer_rsrc_t rs_x = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(ZERO ? a.r : a.xin), 0, nbytes, 0x00020000);
-    const __amdgpu_buffer_rsrc_t rs_o =
-        __builtin_amdgcn_make_buffer_rsrc((void *)a.xout, 0, nbytes, 0x00020000);
     using R = Rec<T>;
     constexpr unsigned RB = R::bytes;
-    const __amdgpu_buffer_rsrc_t rs_b = __builtin_amdgcn_make_buffer_rsrc(
-        a.bnd, 0, (int)(a.bnd_elems * RB), 0x00020000);
     const unsigned ep = a.epoch;
 
     auto xrow = [&](int kq, int uq) -> T * {
         return xr + ((kq + 1) * C27_RU + (uq + 2)) * C27_WP;
+    };
+    auto rrow = [&](int kq, int uq) -> T * {
+        return rr + (kq * C27_TU + uq) * C27_WRP;
     };
     // element index of virtual column 0 of row (j, k); dir steps along it
     auto rowbase = [&](int j, int k) -> int {
@@ -235,7 +245,7 @@ __global__ void __launch_bounds__(64 * NW) c27_tile_kernel(C27Args<T> a)
                           a.ticket_base;
             s_tile = tk < (uint64_t)a.ntiles ? (int)tk : -1;
         }
-        for (int e = tid; e < NRING * C27_WP; e += 64 * NW) xr[e] = zero;
+        for (int e = tid; e < NRING * C27_WP; e += NT) xr[e] = zero;
         __syncthreads();
         const int tile = s_tile;
         if (tile < 0 || aborted) return;
@@ -243,101 +253,182 @@ __global__ void __launch_bounds__(64 * NW) c27_tile_kernel(C27Args<T> a)
         const int ut = tv.x, vt = tv.y;
         const int u0 = C27_TU * ut, k0 = KT * vt;
         const int T0 = 2 * (u0 + k0);  // step of column 0 of row (u0, k0)
-
-        // ---- compute role: row (u0 + cl, k0 + kk) ----
-        const int uc = u0 + cl, kc = k0 + kk, jc = uc - kc;
-        const bool vc = (unsigned)jc < (unsigned)ny && kc < nz;
-        const int sc = 2 * (uc + kc);
-        T *const own = xrow(kk, cl);
-        T *const rown = rr + (kk * C27_TU + cl) * C27_WRP;
-        // boundary rows: u0 + 14, u0 + 15 of every plane (entries 0 ..
-        // 2KT - 1) and u0 .. u0 + 13 of the top plane (2KT .. 2KT + 13)
-        const int ipub = cl >= 14 ? (cl - 14) + 2 * kk
-                                  : (kk == KT - 1 ? 2 * KT + cl : -1);
-        const bool pub = vc && ipub >= 0;
-        const int bout = c27_slot(ut, vt, KT, a.nutb) * a.ns * WB;
-
-        // ---- poll role (wavefront 0, lane < 2KT + 18): a new-value halo row
-        //      and the neighbour tile / entry that publishes it ----
-        int hu = 0, hk = 0, hidx = 0, put = ut, pvt = vt;
-        if (l < 2 * KT) {  // u0 - 2, u0 - 1 of plane k0 + l / 2
-            hu = -2 + (l & 1); hk = l >> 1; hidx = l; put = ut - 1;
-        } else if (l < 2 * KT + 14) {  // plane k0 - 1, u0 .. u0 + 13
-            hu = l - 2 * KT; hk = -1; hidx = 2 * KT + hu; pvt = vt - 1;
-        } else if (l < 2 * KT + 16) {  // plane k0 - 1, u0 + 14, u0 + 15
-            hu = 14 + (l - 2 * KT - 14); hk = -1;
-            hidx = 2 * (KT - 1) + (hu - 14); pvt = vt - 1;
-        } else if (l < 2 * KT + 18) {  // plane k0 - 1, u0 - 2, u0 - 1
-            hu = -2 + (l - 2 * KT - 16); hk = -1;
-            hidx = 2 * (KT - 1) + (hu + 2); put = ut - 1; pvt = vt - 1;
-        }
-        const int hug = u0 + hu, hkg = k0 + hk, hj = hug - hkg;
-        const bool vh = w == 0 && l < 2 * KT + 18 &&
-                        (unsigned)hj < (unsigned)ny && hkg >= 0 && hkg < nz;
-        const int sh = 2 * (hug + hkg);
-        const int T0p = 2 * (C27_TU * put + KT * pvt);
-        const int pbuf =
-            vh ? c27_slot(put, pvt, KT, a.nutb) * a.ns * WB + hidx : 0;
-        T *const hrow = xrow(vh ? hk : 0, vh ? hu : 0);
-        // record index of this lane's entry in slice T_
-        auto pslice = [&](int T_) -> int {
-            const int q = min(max(T_ - T0p, 0), a.ns - 1);
-            return pbuf + q * WB;
-        };
-
-        // ---- step range: the pipelines fill before any row's column 0,
-        //      the last rows' last pieces are stored before the end ----
+        // step range: the first window holding column 0 of the lowest row
+        // (skew T0) is loaded 16 to 23 steps before that column, the first
+        // halo poll (skew T0 - 6) 8 steps before; the last row's last piece
+        // is stored within 8 steps after its last column
         const int T_start = T0 - 6 - C27_PRE;
         const int T_lastc = T0 + 2 * (C27_TU - 1) + 2 * (KT - 1) + nx - 1;
-        const int nblk = (T_lastc + 2 * C27_TU + 2 - T_start + 15) / 16;
+        const int nblk = (T_lastc + 9 - T_start + 15) / 16;
 
-        T xpipe[16], rpipe[16], hpipe[16];
-        typename R::V ppipe[C27_POLL];
+        if (wv < NW) {
+            // ================= compute: row (u0 + cl, k0 + kk) =============
+            const int kk = 4 * wv + sub;
+            const int uc = u0 + cl, kc = k0 + kk, jc = uc - kc;
+            const bool vc = (unsigned)jc < (unsigned)ny && kc < nz;
+            const int sc = 2 * (uc + kc);
+            T *const own = xrow(kk, cl);
+            T *const rown = rrow(kk, cl);
+            // boundary rows: u0 + 14, u0 + 15 of every plane (entries 0 ..
+            // 2KT - 1) and u0 .. u0 + 13 of the top plane (2KT .. 2KT + 13)
+            const int ipub = cl >= 14 ? (cl - 14) + 2 * kk
+                                      : (kk == KT - 1 ? 2 * KT + cl : -1);
+            const bool pub = vc && ipub >= 0;
+            const int bout =
+                c27_slot(ut, vt, KT, a.nutb) * a.ns * WB + ipub - T0 * WB;
+            const __amdgpu_buffer_rsrc_t rs_b =
+                __builtin_amdgcn_make_buffer_rsrc(
+                    a.bnd, 0, (int)(a.bnd_elems * RB), 0x00020000);
+            // carried between steps: F(f) = A(f) + D(f) (F0), A(f + 1) (An)
+            // and B of the next point (Bn); only D(f + 1) = v2 + v3, the
+            // two values written in the previous step, is read on the
+            // critical path
+            T F0 = zero, An = zero, Bn = zero, xprev = zero;
+            for (int blk = 0; blk < nblk; ++blk) {
+                const int Tb = T_start + 16 * blk;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) xpipe[q] = rpipe[q] = hpipe[q] = zero;
-#pragma unroll
-        for (int q = 0; q < C27_POLL; ++q) ppipe[q] = typename R::V{};
-        T Fm = zero, F0 = zero, xprev = zero;
-        int spin_budget = a.spin_limit;
-
-        for (int blk = 0; blk < nblk; ++blk) {
-            const int Tb = T_start + 16 * blk;
-#pragma unroll
-            for (int ph = 0; ph < 16; ++ph) {
-                const int st = Tb + ph;
-                // ---- (1) own rows of this phase: stage x / r windows ----
-                {
-                    const int uL = 4 * (ph & 3) + sub, kL = 4 * w + (ph >> 2);
-                    const int u = u0 + uL, k = k0 + kL, j = u - k;
-                    const bool v = (unsigned)j < (unsigned)ny && k < nz;
-                    const int f = st - 2 * (u + k);
-                    const int cx = f + 8 + cl, cr = f + cl;
-                    xrow(kL, uL)[cx & (C27_W - 1)] = xpipe[ph];
-                    rr[(kL * C27_TU + uL) * C27_WRP + (cr & (C27_WR - 1))] =
-                        rpipe[ph];
-                    const int rb = v ? rowbase(j, k) : 0;
-                    if (!ZERO)
-                        xpipe[ph] = buf_load<T>(rs_x, boff(v, rb, cx + 16));
-                    rpipe[ph] = buf_load<T>(rs_r, boff(v, rb, cr + 16));
+                for (int ph = 0; ph < 16; ++ph) {
+                    const int st = Tb + ph;
+                    const int f = st - sc;
+                    const int c1 = (f + 1) & (C27_W - 1);
+                    const int c2 = (f + 2) & (C27_W - 1);
+                    const T v2 = own[c1 - PS], v3 = own[c1 - RW];
+                    const T v0 = own[c2 - PS - 2 * RW], v1 = own[c2 - PS - RW];
+                    const T v4 = own[c2 + RW], v5 = own[c2 + PS];
+                    const T v6 = own[c2 + PS + RW];
+                    const T v7 = own[c2 + PS + 2 * RW];
+                    const T xo2 = own[c2];
+                    const T rf = rown[f & (C27_WR - 1)];
+                    const T D = v2 + v3;
+                    const T x = c27_combine(rf, Bn, D, xprev, off, inv_diag);
+                    const bool act = vc && (unsigned)f < (unsigned)nx;
+                    if (act) {
+                        own[f & (C27_W - 1)] = x;
+                        xprev = x;
+                    }
+                    R::store(rs_b,
+                             act && pub ? (unsigned)(bout + st * WB) * RB : OOB,
+                             R::make(x, ep));
+                    const T Fp = An + D;  // F(f + 1)
+                    An = ((v0 + v1) + (v4 + v5)) + (v6 + v7);  // A(f + 2)
+                    Bn = (F0 + Fp) + (An + xo2);
+                    F0 = Fp;
+                    __syncthreads();
                 }
-                // ---- (2) old-value halo rows u0 + 16, u0 + 17 of the
-                //      wavefront's planes, and plane k0 + KT (top one) ----
-                if (ph < 13) {
-                    const bool lo = ph < 4;
-                    const bool mine = l < 32 && (lo || w == NW - 1);
-                    const int uH = lo ? 16 + sub : 2 * (ph - 4) + sub;
-                    const int kH = lo ? 4 * w + ph : KT;
-                    const int u = u0 + uH, k = k0 + kH, j = u - k;
-                    const bool v = mine && (unsigned)j < (unsigned)ny &&
-                                   k < nz;
-                    const int cx = st - 2 * (u + k) + 8 + cl;
-                    if (mine) xrow(kH, uH)[cx & (C27_W - 1)] = hpipe[ph];
-                    const int rb = v ? rowbase(j, k) : 0;
-                    if (!ZERO)
-                        hpipe[ph] = buf_load<T>(rs_x, boff(v, rb, cx + 16));
+                if (s_abort) {
+                    aborted = true;
+                    break;
                 }
-                // ---- (3) new-value halo rows from the neighbour tiles ----
-                {
+            }
+        } else if (wv < 2 * NW) {
+            // ====== memory wavefront m: rows of compute wavefront m ======
+            const int m = wv - NW;
+            const __amdgpu_buffer_rsrc_t rs_r =
+                __builtin_amdgcn_make_buffer_rsrc((void *)a.r, 0, nbytes,
+                                                  0x00020000);
+            const __amdgpu_buffer_rsrc_t rs_x =
+                __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)(ZERO ? a.r : a.xin), 0, nbytes, 0x00020000);
+            const __amdgpu_buffer_rsrc_t rs_o =
+                __builtin_amdgcn_make_buffer_rsrc((void *)a.xout, 0, nbytes,
+                                                  0x00020000);
+            // Rows of step T: rho = 8 (T mod 8) + lane / 8, column lane % 8;
+            // each row gets an 8-column window of x_old ([f + 9, f + 17)),
+            // of r ([f + 1, f + 9)) and stores its finished [f - 8, f)
+            // every 8 steps; loads are parked 8 steps in registers.
+            T xpipe[8], rpipe[8], hpipe[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) xpipe[q] = rpipe[q] = hpipe[q] = zero;
+            const int q8 = l & 7, r8 = l >> 3;
+            for (int blk = 0; blk < nblk; ++blk) {
+                const int Tb = T_start + 16 * blk;
+#pragma unroll
+                for (int ph = 0; ph < 16; ++ph) {
+                    const int st = Tb + ph;
+                    const int p8 = ph & 7;
+                    {
+                        const int rho = 8 * p8 + r8;
+                        const int uL = rho & 15, kL = 4 * m + (rho >> 4);
+                        const int u = u0 + uL, k = k0 + kL, j = u - k;
+                        const bool v = (unsigned)j < (unsigned)ny && k < nz;
+                        const int f = st - 2 * (u + k);
+                        const int rb = v ? rowbase(j, k) : 0;
+                        T *const xw = xrow(kL, uL);
+                        const int cx = f + 9 + q8, cr = f + 1 + q8,
+                                  cs = f - 8 + q8;
+                        xw[cx & (C27_W - 1)] = xpipe[p8];
+                        rrow(kL, uL)[cr & (C27_WR - 1)] = rpipe[p8];
+                        const T xv = xw[cs & (C27_W - 1)];
+                        if (!ZERO)
+                            xpipe[p8] = buf_load<T>(rs_x, boff(v, rb, cx + 8));
+                        rpipe[p8] = buf_load<T>(rs_r, boff(v, rb, cr + 8));
+                        buf_store<T, 0>(rs_o, boff(v, rb, cs), xv);
+                    }
+                    // -- old-value halo rows: u0 + 16, u0 + 17 of this
+                    //    wavefront's planes (h < 8) and plane k0 + KT
+                    //    (h = 8 .. 25, last wavefront), 8 rows per step --
+                    if (p8 < 4) {
+                        const int h = 8 * p8 + r8;
+                        const bool lo = h < 8;
+                        const bool mine = lo || (m == NW - 1 && h < 26);
+                        const int uH = lo ? 16 + (h & 1) : h - 8;
+                        const int kH = lo ? 4 * m + (h >> 1) : KT;
+                        const int u = u0 + uH, k = k0 + kH, j = u - k;
+                        const bool v = mine && (unsigned)j < (unsigned)ny &&
+                                       k < nz;
+                        const int cx = st - 2 * (u + k) + 9 + q8;
+                        if (mine) xrow(kH, uH)[cx & (C27_W - 1)] = hpipe[p8];
+                        const int rb = v ? rowbase(j, k) : 0;
+                        if (!ZERO)
+                            hpipe[p8] = buf_load<T>(rs_x, boff(v, rb, cx + 8));
+                    }
+                    __syncthreads();
+                }
+                if (s_abort) {
+                    aborted = true;
+                    break;
+                }
+            }
+        } else {
+            // ====== poll wavefront: lane h < 2KT + 18 owns one new-value
+            //        halo row and the tile / entry that publishes it ======
+            int hu = 0, hk = 0, hidx = 0, put = ut, pvt = vt;
+            if (l < 2 * KT) {  // u0 - 2, u0 - 1 of plane k0 + l / 2
+                hu = -2 + (l & 1); hk = l >> 1; hidx = l; put = ut - 1;
+            } else if (l < 2 * KT + 14) {  // plane k0 - 1, u0 .. u0 + 13
+                hu = l - 2 * KT; hk = -1; hidx = 2 * KT + hu; pvt = vt - 1;
+            } else if (l < 2 * KT + 16) {  // plane k0 - 1, u0 + 14, u0 + 15
+                hu = 14 + (l - 2 * KT - 14); hk = -1;
+                hidx = 2 * (KT - 1) + (hu - 14); pvt = vt - 1;
+            } else if (l < 2 * KT + 18) {  // plane k0 - 1, u0 - 2, u0 - 1
+                hu = -2 + (l - 2 * KT - 16); hk = -1;
+                hidx = 2 * (KT - 1) + (hu + 2); put = ut - 1; pvt = vt - 1;
+            }
+            const int hug = u0 + hu, hkg = k0 + hk, hj = hug - hkg;
+            const bool vh = l < 2 * KT + 18 && (unsigned)hj < (unsigned)ny &&
+                            hkg >= 0 && hkg < nz;
+            const int sh = 2 * (hug + hkg);
+            const int T0p = 2 * (C27_TU * put + KT * pvt);
+            const int pbuf =
+                vh ? c27_slot(put, pvt, KT, a.nutb) * a.ns * WB + hidx : 0;
+            T *const hrow = xrow(vh ? hk : 0, vh ? hu : 0);
+            const __amdgpu_buffer_rsrc_t rs_b =
+                __builtin_amdgcn_make_buffer_rsrc(
+                    a.bnd, 0, (int)(a.bnd_elems * RB), 0x00020000);
+            // record index of this lane's entry in slice T_
+            auto pslice = [&](int T_) -> int {
+                const int q = min(max(T_ - T0p, 0), a.ns - 1);
+                return pbuf + q * WB;
+            };
+            typename R::V ppipe[C27_POLL];
+#pragma unroll
+            for (int q = 0; q < C27_POLL; ++q) ppipe[q] = typename R::V{};
+            int spin_budget = a.spin_limit;
+            for (int blk = 0; blk < nblk; ++blk) {
+                const int Tb = T_start + 16 * blk;
+#pragma unroll
+                for (int ph = 0; ph < 16; ++ph) {
+                    const int st = Tb + ph;
                     const int c = st - sh;
                     if (vh && c >= 0) {
                         T v = zero;
@@ -365,57 +456,12 @@ __global__ void __launch_bounds__(64 * NW) c27_tile_kernel(C27Args<T> a)
                     // poll the slice POLL steps ahead
                     ppipe[ph & (C27_POLL - 1)] = R::load(
                         rs_b, vh ? (unsigned)pslice(st + C27_POLL) * RB : OOB);
-                }
-                // ---- (4) the point at column f of the own row ----
-                {
-                    const int f = st - sc;
-                    const int cw = (f + 1) & (C27_W - 1);
-                    const T v0 = own[cw - PS - 2 * RW], v1 = own[cw - PS - RW];
-                    const T v2 = own[cw - PS], v3 = own[cw - RW];
-                    const T v4 = own[cw + RW], v5 = own[cw + PS];
-                    const T v6 = own[cw + PS + RW];
-                    const T v7 = own[cw + PS + 2 * RW];
-                    const T xon = own[cw];
-                    const T Fp =
-                        ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7));
-                    const T S = (Fm + F0) + (Fp + xon);
-                    T t = fma(-off, S, rown[f & (C27_WR - 1)]);
-                    t = fma(-off, xprev, t);
-                    const T x = t * inv_diag;
-                    const bool act = vc && (unsigned)f < (unsigned)nx;
-                    if (act) {
-                        own[f & (C27_W - 1)] = x;
-                        xprev = x;
-                    }
-                    R::store(rs_b,
-                             act && pub ? (unsigned)(bout + (st - T0) * WB +
-                                                     ipub) * RB
-                                        : OOB,
-                             R::make(x, ep));
-                    Fm = F0;
-                    F0 = Fp;
-                }
-                // ---- (5) the rows staged 8 steps ago store their last 16
-                //      finished columns ----
-                {
-                    const int ps = ph ^ 8;
-                    const int uS = 4 * (ps & 3) + sub, kS = 4 * w + (ps >> 2);
-                    const int u = u0 + uS, k = k0 + kS, j = u - k;
-                    const bool v = (unsigned)j < (unsigned)ny && k < nz;
-                    const int c = st - 2 * (u + k) - 16 + cl;
-                    const T xv = xrow(kS, uS)[c & (C27_W - 1)];
-                    const int rb = v ? rowbase(j, k) : 0;
-                    buf_store<T, 0>(rs_o, boff(v, rb, c), xv);
-                }
-                if constexpr (NW > 1)
                     __syncthreads();
-                else
-                    asm volatile("" ::: "memory");
-            }
-            if constexpr (NW == 1) __syncthreads();
-            if (s_abort) {
-                aborted = true;
-                break;
+                }
+                if (s_abort) {
+                    aborted = true;
+                    break;
+                }
             }
         }
     }
@@ -448,6 +494,8 @@ C27Layout c27_layout(Grid g, int nw)
     return L;
 }
 
+int c27_threads(int nw) { return 64 * (2 * nw + 1); }
+
 size_t c27_lds_bytes(int nw, m2s_dtype t)
 {
     const int kt = 4 * nw;
@@ -470,7 +518,7 @@ static hipError_t c27_launch_t(const C27Args<T> &a, int grid, size_t lds,
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * NW), lds, s, a);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * (2 * NW + 1)), lds, s, a);
     return hipGetLastError();
 }
 

@@ -84,6 +84,21 @@ struct SweepPlan {
     int grid;         // workgroups launched (<= nslabs)
 };
 
+// x_i = (r_i - off * (S + x_new(i-1))) / diag, evaluated as
+//   B  = (F(i-1) + F(i)) + (A(i+1) + x_old(i+1))
+//   S  = B + D(i+1)
+//   x_i = fma(-off, S, fma(-off, x_new(i-1), r_i)) * (1 / diag),
+// the association of every 27-point sweep kernel (the sequential one and
+// the tiled wavefront one use this same function).
+template <typename T>
+__device__ __forceinline__ T c27_combine(T r, T B, T Dp, T xn_prev, T off,
+                                         T inv_diag)
+{
+    const T S = B + Dp;
+    const T t1 = fma(-off, xn_prev, r);
+    return fma(-off, S, t1) * inv_diag;
+}
+
 // Workspace (opaque in the ABI).
 struct Workspace {
     m2s_kind kind;
@@ -158,6 +173,7 @@ struct C27Layout {
 };
 C27Layout c27_layout(Grid g, int nw);
 size_t c27_lds_bytes(int nw, m2s_dtype t);
+int c27_threads(int nw);  // nw compute + nw memory + 1 poll wavefronts
 // bytes of one boundary record: the value and the launch epoch
 inline size_t c27_record_bytes(m2s_dtype t) { return t == M2S_F64 ? 16 : 8; }
 

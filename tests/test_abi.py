@@ -58,7 +58,8 @@ def test_plan_shapes(n):
     # one lane per row
     assert p["row_slots"] == 16
     assert p["slab_planes"] % 4 == 0
-    assert p["threads"] == 16 * p["slab_planes"]
+    # nw = slab_planes / 4 compute, nw memory and 1 poll wavefronts
+    assert p["threads"] == 64 * (2 * (p["slab_planes"] // 4) + 1)
     assert p["nslabs"] == len(c27_tiles((n, n, n), p["slab_planes"]))
 
 

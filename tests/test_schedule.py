@@ -152,7 +152,7 @@ def test_gpu_schedule_satisfies_all_dependences(kind, shape, bk, monkeypatch):
 # written by one wavefront and touched by another in the same step; and
 # every point must be stored exactly once, with its new value.
 # ---------------------------------------------------------------------------
-TU, RU, W, WR, POLL, PRE = 16, 20, 32, 16, 8, 48
+TU, RU, W, WR, POLL, PRE = 16, 20, 32, 16, 4, 18
 
 
 def c27_tile_list(shape, kt):
@@ -168,6 +168,9 @@ def c27_tile_list(shape, kt):
 
 
 def simulate_c27_tiles(shape, nw, zero_start=False):
+    """Wavefronts 0 .. nw-1 compute (one lane per row), nw .. 2nw-1 memory
+    (wavefront nw + m stages x_old / r of compute wavefront m's rows and
+    stores its pieces), 2nw polls the neighbour tiles' boundary records."""
     nz, ny, nx = shape
     KT = 4 * nw
     tiles = c27_tile_list(shape, KT)
@@ -182,93 +185,107 @@ def simulate_c27_tiles(shape, nw, zero_start=False):
             return 0
         return ("old", u - k, k, c)
 
+    def xslot(kq, uq, c):
+        return ((kq + 1) * RU + (uq + 2), c % W)
+
     for (ut, vt) in tiles:
         u0, k0 = TU * ut, KT * vt
         T0 = 2 * (u0 + k0)
-        xr, rr = {}, {}          # slot -> (value, step, wave)
+        xr, rr = {}, {}
         T_start = T0 - 6 - PRE
         T_lastc = T0 + 2 * (TU - 1) + 2 * (KT - 1) + nx - 1
-        nblk = (T_lastc + 2 * TU + 2 - T_start + 15) // 16
-        F = {}                   # lane -> [Fm, F0] column tags
+        nblk = (T_lastc + 9 - T_start + 15) // 16
         for blk in range(nblk):
             for ph in range(16):
                 T = T_start + 16 * blk + ph
-                writes = []      # (ring, slot, value, wave, role)
-                reads = []       # (ring, slot, wave, role, expected)
-
-                def xslot(kq, uq, c):
-                    return ((kq + 1) * RU + (uq + 2), c % W)
-
+                writes = []      # (ring, slot, value, wave)
+                reads = []       # (ring, slot, wave, expected)
+                for m in range(nw):
+                    wm = nw + m
+                    for lane in range(64):
+                        q8, r8, p8 = lane & 7, lane >> 3, ph & 7
+                        # 8 rows per step: x_old window [f + 8, f + 16),
+                        # r window [f + 1, f + 9), store [f - 8, f)
+                        rho = 8 * p8 + r8
+                        uL, kL = rho & 15, 4 * m + (rho >> 4)
+                        u, k = u0 + uL, k0 + kL
+                        f = T - 2 * (u + k)
+                        cx, cr, cs = f + 9 + q8, f + 1 + q8, f - 8 + q8
+                        vx = 0 if T - 8 < T_start else old(u, k, cx)
+                        writes.append(("x", xslot(kL, uL, cx), vx, wm))
+                        vr = (0 if T - 8 < T_start or not valid(u, k) or
+                              not 0 <= cr < nx else ("r", u - k, k, cr))
+                        writes.append(("r", (kL * TU + uL, cr % WR), vr, wm))
+                        if valid(u, k) and 0 <= cs < nx:
+                            reads.append(("x", xslot(kL, uL, cs), wm,
+                                          ("new", u - k, k, cs)))
+                            key = (k, u - k, cs)
+                            assert key not in stored, key
+                            stored[key] = True
+                        # old-value halo rows
+                        if p8 < 4:
+                            h = 8 * p8 + r8
+                            lo = h < 8
+                            if lo or (m == nw - 1 and h < 26):
+                                uH = 16 + (h & 1) if lo else h - 8
+                                kH = 4 * m + (h >> 1) if lo else KT
+                                cxh = T - 2 * (u0 + uH + k0 + kH) + 9 + q8
+                                vh = (0 if T - 8 < T_start else
+                                      old(u0 + uH, k0 + kH, cxh))
+                                writes.append(("x", xslot(kH, uH, cxh), vh,
+                                               wm))
+                # poll wavefront
+                wp = 2 * nw
+                for lane in range(2 * KT + 18):
+                    if lane < 2 * KT:
+                        hu, hk = -2 + (lane & 1), lane >> 1
+                        prod, hidx = (ut - 1, vt), lane
+                    elif lane < 2 * KT + 14:
+                        hu, hk = lane - 2 * KT, -1
+                        prod, hidx = (ut, vt - 1), 2 * KT + hu
+                    elif lane < 2 * KT + 16:
+                        hu, hk = 14 + lane - 2 * KT - 14, -1
+                        prod = (ut, vt - 1)
+                        hidx = 2 * (KT - 1) + hu - 14
+                    else:
+                        hu, hk = -2 + lane - 2 * KT - 16, -1
+                        prod = (ut - 1, vt - 1)
+                        hidx = 2 * (KT - 1) + hu + 2
+                    hug, hkg = u0 + hu, k0 + hk
+                    c = T - 2 * (hug + hkg)
+                    if valid(hug, hkg) and c >= 0:
+                        if c < nx:
+                            # the record was polled POLL steps earlier
+                            assert T - POLL >= T_start, (T, T_start)
+                            assert prod in ticket and \
+                                ticket[prod] < ticket[(ut, vt)]
+                            # the producer publishes this row at entry hidx
+                            uup = hug - TU * prod[0]
+                            kkp = hkg - KT * prod[1]
+                            assert 0 <= uup < TU and 0 <= kkp < KT
+                            ent = ((uup - 14) + 2 * kkp if uup >= 14 else
+                                   (2 * KT + uup if kkp == KT - 1 else -1))
+                            assert ent == hidx, (ent, hidx)
+                            v = ("new", hug - hkg, hkg, c)
+                        else:
+                            v = 0
+                        writes.append(("x", xslot(hk, hu, c), v, wp))
+                # compute wavefronts
                 for w in range(nw):
                     for lane in range(64):
                         sub, cl = lane >> 4, lane & 15
-                        # (1) own rows of this phase
-                        uL, kL = 4 * (ph & 3) + sub, 4 * w + (ph >> 2)
-                        u, k = u0 + uL, k0 + kL
-                        f = T - 2 * (u + k)
-                        cx, cr = f + 8 + cl, f + cl
-                        # value loaded one cycle ago for the same column
-                        vx = 0 if T - 16 < T_start else old(u, k, cx)
-                        writes.append(("x", xslot(kL, uL, cx), vx, w, 1))
-                        vr = (0 if T - 16 < T_start or not valid(u, k) or
-                              not 0 <= cr < nx else ("r", u - k, k, cr))
-                        writes.append(("r", ((kL * TU + uL), cr % WR), vr,
-                                       w, 1))
-                        # (2) old-value halo rows
-                        if lane < 32 and (ph < 4 or (w == nw - 1 and
-                                                     ph < 13)):
-                            lo = ph < 4
-                            uH = 16 + sub if lo else 2 * (ph - 4) + sub
-                            kH = 4 * w + ph if lo else KT
-                            cxh = T - 2 * (u0 + uH + k0 + kH) + 8 + cl
-                            vh = (0 if T - 16 < T_start else
-                                  old(u0 + uH, k0 + kH, cxh))
-                            writes.append(("x", xslot(kH, uH, cxh), vh, w, 2))
-                        # (3) new-value halo rows (wavefront 0)
-                        if w == 0 and lane < 2 * KT + 18:
-                            if lane < 2 * KT:
-                                hu, hk = -2 + (lane & 1), lane >> 1
-                                prod, hidx = (ut - 1, vt), lane
-                            elif lane < 2 * KT + 14:
-                                hu, hk = lane - 2 * KT, -1
-                                prod, hidx = (ut, vt - 1), 2 * KT + hu
-                            elif lane < 2 * KT + 16:
-                                hu, hk = 14 + lane - 2 * KT - 14, -1
-                                prod = (ut, vt - 1)
-                                hidx = 2 * (KT - 1) + hu - 14
-                            else:
-                                hu, hk = -2 + lane - 2 * KT - 16, -1
-                                prod = (ut - 1, vt - 1)
-                                hidx = 2 * (KT - 1) + hu + 2
-                            hug, hkg = u0 + hu, k0 + hk
-                            c = T - 2 * (hug + hkg)
-                            if valid(hug, hkg) and c >= 0:
-                                if c < nx:
-                                    assert prod in ticket and \
-                                        ticket[prod] < ticket[(ut, vt)]
-                                    # the producer publishes this row at
-                                    # entry hidx of its slice
-                                    uup = hug - TU * prod[0]
-                                    kkp = hkg - KT * prod[1]
-                                    assert 0 <= uup < TU and 0 <= kkp < KT
-                                    ent = ((uup - 14) + 2 * kkp if uup >= 14
-                                           else (2 * KT + uup
-                                                 if kkp == KT - 1 else -1))
-                                    assert ent == hidx, (ent, hidx)
-                                    v = ("new", hug - hkg, hkg, c)
-                                else:
-                                    v = 0
-                                writes.append(("x", xslot(hk, hu, c), v, w,
-                                               3))
-                        # (4) compute
                         kk = 4 * w + sub
                         u, k = u0 + cl, k0 + kk
                         f = T - 2 * (u + k)
-                        c = f + 1
-                        nbrs = [(-2, -1), (-1, -1), (0, -1), (-1, 0),
-                                (1, 0), (0, 1), (1, 1), (2, 1)]
-                        exp = []
-                        for du, dk in nbrs:
+                        # v2 (u, k-1) and v3 (u-1, k) of column f + 1 are
+                        # read last; the other six rows and the own old
+                        # value are read for column f + 2
+                        for du, dk, c in ((0, -1, f + 1), (-1, 0, f + 1),
+                                          (-2, -1, f + 2), (-1, -1, f + 2),
+                                          (1, 0, f + 2), (0, 1, f + 2),
+                                          (1, 1, f + 2), (2, 1, f + 2)):
+                            if not (valid(u, k) and -1 <= c <= nx):
+                                continue
                             ua, ka = u + du, k + dk
                             lower = dk < 0 or (dk == 0 and du < 0)
                             if not valid(ua, ka) or not 0 <= c < nx:
@@ -278,45 +295,31 @@ def simulate_c27_tiles(shape, nw, zero_start=False):
                             else:
                                 e = old(ua, ka, c)
                             reads.append(("x", xslot(kk + dk, cl + du, c), w,
-                                          4, e))
-                        if valid(u, k) and -2 <= f < nx:
-                            reads.append(("x", xslot(kk, cl, c), w, 4,
+                                          e))
+                        c = f + 2
+                        if valid(u, k) and -1 <= c <= nx:
+                            reads.append(("x", xslot(kk, cl, c), w,
                                           old(u, k, c) if c < nx else 0))
                         if valid(u, k) and 0 <= f < nx:
-                            reads.append(("r", ((kk * TU + cl), f % WR), w,
-                                          4, ("r", u - k, k, f)))
+                            reads.append(("r", (kk * TU + cl, f % WR), w,
+                                          ("r", u - k, k, f)))
                             writes.append(("x", xslot(kk, cl, f),
-                                           ("new", u - k, k, f), w, 4))
-                        # (5) stores of the rows staged 8 steps ago
-                        ps = ph ^ 8
-                        uS, kS = 4 * (ps & 3) + sub, 4 * w + (ps >> 2)
-                        u, k = u0 + uS, k0 + kS
-                        c = T - 2 * (u + k) - 16 + cl
-                        if valid(u, k) and 0 <= c < nx:
-                            reads.append(("x", xslot(kS, uS, c), w, 5,
-                                          ("new", u - k, k, c)))
-                            key = (k, u - k, c)
-                            assert key not in stored, key
-                            stored[key] = True
-                # same-step hazards between wavefronts
+                                           ("new", u - k, k, f), w))
+                # one step: no slot is touched by two wavefronts if one of
+                # them writes it; reads see the previous step's state
                 wsl = {}
-                for ring, slot, v, w, role in writes:
+                for ring, slot, v, w in writes:
                     prev = wsl.get((ring, slot))
-                    if prev is not None:
-                        assert prev[1] == w, ("write race", ring, slot, T)
-                    wsl[(ring, slot)] = (v, w, role)
-                for ring, slot, w, role, e in reads:
-                    wr = wsl.get((ring, slot))
+                    assert prev is None or prev[1] == w, \
+                        ("write race", ring, slot, T)
+                    wsl[(ring, slot)] = (v, w)
+                for ring, slot, w, e in reads:
+                    assert (ring, slot) not in wsl, \
+                        ("read/write race", ring, slot, T, w, wsl[(ring, slot)])
                     mem = xr if ring == "x" else rr
-                    if wr is not None:
-                        assert wr[1] == w, ("read/write race", ring, slot, T)
-                        got = wr[0] if wr[2] < role else mem.get(slot, 0)
-                    else:
-                        got = mem.get(slot, 0)
-                    if role == 4 and e is not None:
-                        pass
-                    assert got == e, (T, ring, slot, role, got, e)
-                for (ring, slot), (v, w, role) in wsl.items():
+                    got = mem.get(slot, 0)
+                    assert got == e, (T, ring, slot, got, e)
+                for (ring, slot), (v, w) in wsl.items():
                     (xr if ring == "x" else rr)[slot] = v
     for k in range(nz):
         for j in range(ny):
@@ -363,5 +366,7 @@ def test_c27_plan_matches_tile_model(shape, monkeypatch):
     for nw in (1, 2, 4):
         monkeypatch.setenv("M2S_C27_WAVES", str(nw))
         p = m.plan_sweep(m.const27(shape))
-        assert p["slab_planes"] == 4 * nw and p["threads"] == 64 * nw
+        assert p["slab_planes"] == 4 * nw
+        # nw compute + nw memory wavefronts + 1 poll wavefront
+        assert p["threads"] == 64 * (2 * nw + 1)
         assert p["nslabs"] == len(c27_tile_list(shape, 4 * nw))
