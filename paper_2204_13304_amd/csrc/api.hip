@@ -162,6 +162,34 @@ m2s_status make_plan(const m2s_stencil &A, SweepPlan &P, bool with_grid)
             P.grid = std::max(1, std::min(P.nslabs, cus * per_cu));
         }
         return M2S_OK;
+    } else if (A.kind == M2S_BLOCK7_5) {
+        // rectangular tiles of 16 j by 4 * nw k, one lane per row
+        if ((int64_t)nx * ny * nz * 40 >= ((int64_t)1 << 31))
+            return M2S_ERR_SHAPE;
+        // one compute wavefront (4 planes) per tile: with its two memory
+        // wavefronts and the poll wavefront that is one per SIMD, which
+        // keeps the block arithmetic and the 4-step load pipelines in
+        // registers
+        int nw = env_int("M2S_B7_WAVES", 1);
+        if (nw != 1 && nw != 2) nw = 1;
+        const B7Layout L = b7_layout(Grid{nx, ny, nz}, nw);
+        if (L.bnd_elems * 16 >= ((int64_t)1 << 31)) return M2S_ERR_SHAPE;
+        P.row_slots = 16;
+        P.slab_planes = L.kt;
+        P.nslabs = L.ntiles;
+        P.threads = b7_threads(nw);
+        P.publish_every = 1;
+        P.grid = 0;
+        if (with_grid) {
+            int dev = 0, cus = 0;
+            if (hipGetDevice(&dev) != hipSuccess) return M2S_ERR_HIP;
+            if (hipDeviceGetAttribute(&cus,
+                                      hipDeviceAttributeMultiprocessorCount,
+                                      dev) != hipSuccess)
+                return M2S_ERR_HIP;
+            P.grid = std::max(1, std::min(P.nslabs, cus));
+        }
+        return M2S_OK;
     } else {
         R = (nx + P.lag_row - 1) / P.lag_row;
         if (R > ny) R = ny;
@@ -169,8 +197,7 @@ m2s_status make_plan(const m2s_stencil &A, SweepPlan &P, bool with_grid)
         if (bk <= 0) {
             // enough rows per workgroup to fill a CU without serialising too
             // much of the plane chain on one workgroup
-            const int target = A.kind == M2S_BLOCK7_5 ? 256 : 512;
-            bk = std::max(1, std::min(8, target / R));
+            bk = std::max(1, std::min(8, 512 / R));
         }
         if (bk * R > kMaxThreads) bk = kMaxThreads / R;
     }
@@ -206,38 +233,49 @@ m2s_status check_ws(const m2s_stencil &A, const m2s_workspace *ws)
     return M2S_OK;
 }
 
-// The 27-point sweep's tile table and boundary store, laid out for nw
-// wavefronts per tile; rebuilt (synchronously) when nw changes.
-m2s_status ensure_c27(m2s_workspace *ws, int nw)
+// The tiled sweeps' tile table (27 points) and boundary store, laid out for
+// nw compute wavefronts per tile; rebuilt (synchronously) when nw changes.
+m2s_status ensure_tiles(m2s_workspace *ws, int nw)
 {
-    if (ws->bnd && ws->c27_nw == nw) return M2S_OK;
-    if (ws->bnd || ws->c27_tiles) {
+    if (ws->bnd && ws->tile_nw == nw) return M2S_OK;
+    if (ws->bnd || ws->tile_list) {
         if (hipDeviceSynchronize() != hipSuccess) return M2S_ERR_HIP;
         if (ws->bnd) (void)hipFree(ws->bnd);
-        if (ws->c27_tiles) (void)hipFree(ws->c27_tiles);
+        if (ws->tile_list) (void)hipFree(ws->tile_list);
         ws->bnd = nullptr;
-        ws->c27_tiles = nullptr;
+        ws->tile_list = nullptr;
     }
-    const C27Layout L = c27_layout(ws->g, nw);
-    const int64_t n = std::max<int64_t>(L.bnd_elems, 1);
-    const size_t tb = sizeof(int2) * std::max<size_t>(L.tiles.size(), 1);
-    const size_t rb = c27_record_bytes(ws->dtype);
+    int64_t n = 1;
+    size_t rb = 16;
+    std::vector<int2> tiles;
+    if (ws->kind == M2S_CONST27) {
+        C27Layout L = c27_layout(ws->g, nw);
+        n = std::max<int64_t>(L.bnd_elems, 1);
+        rb = c27_record_bytes(ws->dtype);
+        tiles.swap(L.tiles);
+        ws->tile_ntiles = (int)tiles.size();
+        ws->tile_nutb = L.nutb;
+        ws->tile_ns = L.ns;
+    } else {
+        const B7Layout L = b7_layout(ws->g, nw);
+        n = std::max<int64_t>(L.bnd_elems, 1);
+        ws->tile_ntiles = L.ntiles;
+        ws->tile_nutb = L.njt;
+        ws->tile_ns = L.ns;
+    }
+    const size_t tb = sizeof(int2) * std::max<size_t>(tiles.size(), 1);
     // records start with epoch 0, which no launch uses
     if (hipMalloc(&ws->bnd, n * rb) != hipSuccess ||
-        hipMalloc(&ws->c27_tiles, tb) != hipSuccess)
+        hipMalloc(&ws->tile_list, tb) != hipSuccess)
         return M2S_ERR_HIP;
-    if ((!L.tiles.empty() &&
-         hipMemcpy(ws->c27_tiles, L.tiles.data(),
-                   sizeof(int2) * L.tiles.size(),
+    if ((!tiles.empty() &&
+         hipMemcpy(ws->tile_list, tiles.data(), sizeof(int2) * tiles.size(),
                    hipMemcpyHostToDevice) != hipSuccess) ||
         hipMemset(ws->bnd, 0, n * rb) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess)
         return M2S_ERR_HIP;
     ws->bnd_elems = n;
-    ws->c27_nw = nw;
-    ws->c27_ntiles = (int)L.tiles.size();
-    ws->c27_nutb = L.nutb;
-    ws->c27_ns = L.ns;
+    ws->tile_nw = nw;
     return M2S_OK;
 }
 
@@ -250,10 +288,9 @@ m2s_status half_sweep(const m2s_stencil &A, const Block7Consts *b7,
     SweepPlan P{};
     m2s_status st = make_plan(A, P, true);
     if (st != M2S_OK) return st;
-    if (A.kind != M2S_CONST27 && P.nslabs > ws->nflags)
-        return M2S_ERR_SHAPE;
-    if (A.kind == M2S_CONST27 &&
-        (st = ensure_c27(ws, P.slab_planes / 4)) != M2S_OK)
+    const bool tiled = A.kind == M2S_CONST27 || A.kind == M2S_BLOCK7_5;
+    if (!tiled && P.nslabs > ws->nflags) return M2S_ERR_SHAPE;
+    if (tiled && (st = ensure_tiles(ws, P.slab_planes / 4)) != M2S_OK)
         return st;
     return hip_status(launch_sweep(A, b7, omega, r, xin, xout, bwd, zero_init,
                                    *ws, P, s));
@@ -298,6 +335,8 @@ m2s_status m2s_plan_sweep(const m2s_stencil *A, m2s_sweep_plan *plan)
     if (A->kind == M2S_CONST27)  // u = j + k: T = i + 2u + 2k
         plan->steps = A->ext.nx + 2 * (P.row_slots - 1) +
                       2 * (P.slab_planes - 1);
+    else if (A->kind == M2S_BLOCK7_5)  // T = i + j + k within a tile
+        plan->steps = A->ext.nx + (P.row_slots - 1) + (P.slab_planes - 1);
     else
         plan->steps = A->ext.nx + P.lag_row * (A->ext.ny - 1) +
                       P.lag_plane * (P.slab_planes - 1);
@@ -327,14 +366,14 @@ m2s_status m2s_workspace_create(const m2s_stencil *A, m2s_workspace **out)
               hipMalloc(&ws->err, sizeof(int)) == hipSuccess &&
               hipMalloc(&ws->scratch, vb) == hipSuccess &&
               hipMalloc(&ws->scratch2, vb) == hipSuccess;
-    if (ok && A->kind == M2S_CONST27) {
+    if (ok && (A->kind == M2S_CONST27 || A->kind == M2S_BLOCK7_5)) {
         SweepPlan P{};
         const m2s_status pst = make_plan(*A, P, false);
         if (pst != M2S_OK) {
             m2s_workspace_destroy(ws);
             return pst;
         }
-        ok = ensure_c27(ws, P.slab_planes / 4) == M2S_OK;
+        ok = ensure_tiles(ws, P.slab_planes / 4) == M2S_OK;
     }
     ok = ok && hipMemset(ws->flags, 0, sizeof(uint64_t) * ws->nflags) ==
                    hipSuccess &&
@@ -359,7 +398,8 @@ void m2s_workspace_destroy(m2s_workspace *ws)
     if (ws->scratch) (void)hipFree(ws->scratch);
     if (ws->scratch2) (void)hipFree(ws->scratch2);
     if (ws->bnd) (void)hipFree(ws->bnd);
-    if (ws->c27_tiles) (void)hipFree(ws->c27_tiles);
+    if (ws->tile_list) (void)hipFree(ws->tile_list);
+    if (ws->b7c) (void)hipFree(ws->b7c);
     delete ws;
 }
 

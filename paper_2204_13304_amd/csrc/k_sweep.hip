@@ -129,58 +129,32 @@ __device__ __forceinline__ void b7_point(const Virt<BWD> &V,
                                          const double *xo, double *out,
                                          int iv, int jv, int kv)
 {
+    // sweep coordinates: (iv, jv, kv) - 1 are updated, + 1 are not
     const Grid &g = V.g;
-    const int i = V.ri(iv), j = V.rj(jv), k = V.rk(kv);
-    const int64_t p = g.idx(i, j, k);
-    const double *lo = BWD ? xo : xn;
-    const double *hi = BWD ? xn : xo;
-    double s[5];
+    const int64_t p = V.idx(iv, jv, kv);
+    const int di[6] = {1, 0, 0, -1, 0, 0};
+    const int dj[6] = {0, 1, 0, 0, -1, 0};
+    const int dk[6] = {0, 0, 1, 0, 0, -1};
+    double xq[6][5], bb[5], old[5], res[5];
+    bool has[6];
 #pragma unroll
-    for (int a = 0; a < 5; ++a) s[a] = b[5 * p + a];
-    const int di[7] = {0, -1, 1, 0, 0, 0, 0};
-    const int dj[7] = {0, 0, 0, -1, 1, 0, 0};
-    const int dk[7] = {0, 0, 0, 0, 0, -1, 1};
+    for (int v = 0; v < 6; ++v) {
+        const int ii = iv + di[v], jj = jv + dj[v], kk = kv + dk[v];
+        has[v] = g.in(ii, jj, kk);
+        const double *src = v < 3 ? xo : xn;
+        const int64_t q = has[v] ? 5 * V.idx(ii, jj, kk) : 0;
 #pragma unroll
-    for (int d = 1; d < 7; ++d) {
-        const int ii = i + di[d], jj = j + dj[d], kk = k + dk[d];
-        if (!g.in(ii, jj, kk)) continue;
-        const double *src = (d & 1) ? lo : hi;  // odd d: -x,-y,-z
-        const int64_t q = 5 * g.idx(ii, jj, kk);
-        double xq[5];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) xq[c] = src ? src[q + c] : 0.0;
-#pragma unroll
-        for (int a = 0; a < 5; ++a)
-#pragma unroll
-            for (int c = 0; c < 5; ++c)
-                s[a] = fma(-C.B[d][5 * a + c], xq[c], s[a]);
-    }
-    // y = U^{-1} L^{-1} P s
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        const int pc = C.piv[c];
-        if (pc != c) {
-            double t = s[c];
-#pragma unroll
-            for (int q = 0; q < 5; ++q)
-                if (q == pc) { s[c] = s[q]; s[q] = t; }
-        }
-    }
-#pragma unroll
-    for (int a = 1; a < 5; ++a)
-#pragma unroll
-        for (int c = 0; c < a; ++c) s[a] = fma(-C.lu[5 * a + c], s[c], s[a]);
-#pragma unroll
-    for (int a = 4; a >= 0; --a) {
-#pragma unroll
-        for (int c = a + 1; c < 5; ++c) s[a] = fma(-C.lu[5 * a + c], s[c], s[a]);
-        s[a] = s[a] * C.inv_udiag[a];
+        for (int c = 0; c < 5; ++c)
+            xq[v][c] = (has[v] && src) ? src[q + c] : 0.0;
     }
 #pragma unroll
     for (int a = 0; a < 5; ++a) {
-        const double old = xo ? xo[5 * p + a] : 0.0;
-        out[5 * p + a] = fma(w, s[a], (1.0 - w) * old);
+        bb[a] = b[5 * p + a];
+        old[a] = xo ? xo[5 * p + a] : 0.0;
     }
+    b7_combine<BWD>(C, w, bb, xq, has, old, res);
+#pragma unroll
+    for (int a = 0; a < 5; ++a) out[5 * p + a] = res[a];
 }
 
 // --------------------------------------------------------------------------
@@ -389,8 +363,8 @@ hipError_t launch_sweep(const m2s_stencil &A, const Block7Consts *b7,
                    : launch_typed<KIND_V7, float>(A, b7, omega, r, xin, xout,
                                                   bwd, ws, plan, s);
     case M2S_BLOCK7_5:
-        return launch_typed<KIND_B7, double>(A, b7, omega, r, xin, xout, bwd,
-                                             ws, plan, s);
+        if (!b7) return hipErrorInvalidValue;
+        return launch_sweep7(A, *b7, omega, r, xin, xout, bwd, ws, plan, s);
     }
     return hipErrorInvalidValue;
 }

@@ -560,9 +560,9 @@ hipError_t launch_sweep27(const m2s_stencil &A, const void *r,
     auto fill = [&](auto &a) {
         a.g = Grid{A.ext.nx, A.ext.ny, A.ext.nz};
         a.ntiles = plan.nslabs;
-        a.nutb = ws.c27_nutb;
-        a.ns = ws.c27_ns;
-        a.tiles = ws.c27_tiles;
+        a.nutb = ws.tile_nutb;
+        a.ns = ws.tile_ns;
+        a.tiles = ws.tile_list;
         a.ticket = ws.ticket;
         a.ticket_base = base;
         a.err = ws.err;

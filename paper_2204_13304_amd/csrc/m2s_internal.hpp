@@ -99,6 +99,68 @@ __device__ __forceinline__ T c27_combine(T r, T B, T Dp, T xn_prev, T off,
     return fma(-off, S, t1) * inv_diag;
 }
 
+// One block-SSOR point (the NPB-LU-shaped BLOCK7x5 operator, Sec. 7.1):
+//   s = b - sum over in-grid neighbours q of B_d x_q
+//   x = (1 - w) x_old + w D^{-1} s          (D^{-1} via the LU of B_0).
+// xq holds the neighbours by sweep direction, in the order +x, +y, +z
+// (not yet updated) and -x, -y, -z (updated); they are accumulated in that
+// order, so the values written by the sweep's previous step come last.  In a
+// backward sweep the sweep's +x is the grid's -x, so it takes the -x block.
+// Neighbours outside the grid (has[v] false) are skipped.  Every block-SSOR
+// sweep kernel calls this function.
+template <bool BWD>
+__device__ __forceinline__ void b7_combine(const Block7Consts &C, double w,
+                                           const double (&b)[5],
+                                           const double (&xq)[6][5],
+                                           const bool (&has)[6],
+                                           const double (&old)[5],
+                                           double (&out)[5])
+{
+    double s[5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) s[a] = b[a];
+#pragma unroll
+    for (int v = 0; v < 6; ++v) {
+        // grid direction of sweep direction v: 1 -x, 2 +x, 3 -y, ..., 6 +z
+        const int d = BWD ? 2 * (v % 3) + (v < 3 ? 1 : 2)
+                          : 2 * (v % 3) + (v < 3 ? 2 : 1);
+        // a neighbour outside the grid contributes a zero operand rather
+        // than a skipped block, so that the coefficient reads stay in
+        // uniform control flow (scalar loads)
+        double xv[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) xv[c] = has[v] ? xq[v][c] : 0.0;
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+                s[a] = fma(-C.B[d][5 * a + c], xv[c], s[a]);
+    }
+    // s = U^{-1} L^{-1} P s
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        const int pc = C.piv[c];
+        if (pc != c) {
+            double t = s[c];
+#pragma unroll
+            for (int q = 0; q < 5; ++q)
+                if (q == pc) { s[c] = s[q]; s[q] = t; }
+        }
+    }
+#pragma unroll
+    for (int a = 1; a < 5; ++a)
+#pragma unroll
+        for (int c = 0; c < a; ++c) s[a] = fma(-C.lu[5 * a + c], s[c], s[a]);
+#pragma unroll
+    for (int a = 4; a >= 0; --a) {
+#pragma unroll
+        for (int c = a + 1; c < 5; ++c) s[a] = fma(-C.lu[5 * a + c], s[c], s[a]);
+        s[a] = s[a] * C.inv_udiag[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 5; ++a) out[a] = fma(w, s[a], (1.0 - w) * old[a]);
+}
+
 // Workspace (opaque in the ABI).
 struct Workspace {
     m2s_kind kind;
@@ -112,11 +174,14 @@ struct Workspace {
     void *scratch2;     // second vector (adjoint chains)
     void *bnd;          // 27-point sweep: tile boundary store (records)
     int64_t bnd_elems;  // records
-    int c27_nw;         // wavefronts per tile the store was laid out for
-    int c27_ntiles;
-    int c27_nutb;       // boundary-store tile slots per k-tile
-    int c27_ns;         // boundary slices per tile
-    int2 *c27_tiles;    // (u-tile, k-tile) per ticket, device
+    int tile_nw;        // compute wavefronts per tile of the layout
+    int tile_ntiles;
+    int tile_nutb;      // boundary-store tile slots per k-tile
+    int tile_ns;        // boundary slices per tile
+    int2 *tile_list;    // 27-point: (u-tile, k-tile) per ticket, device
+    void *b7c;          // block SSOR: device copy of the block constants
+    Block7Consts b7c_host;
+    bool b7c_valid;
     int64_t nflags;
     uint32_t epoch;
     uint64_t ticket_base;
@@ -174,6 +239,19 @@ struct C27Layout {
 C27Layout c27_layout(Grid g, int nw);
 size_t c27_lds_bytes(int nw, m2s_dtype t);
 int c27_threads(int nw);  // nw compute + nw memory + 1 poll wavefronts
+// Tiling of the block SSOR sweep: rectangular tiles of 16 j by 4 * nw k.
+struct B7Layout {
+    int nw, kt, njt, nbands, ntiles, ns, wb;
+    int64_t bnd_elems;
+};
+B7Layout b7_layout(Grid g, int nw);
+size_t b7_lds_bytes(int nw);
+int b7_threads(int nw);  // nw compute + 2 nw memory + 1 poll wavefronts
+hipError_t launch_sweep7(const m2s_stencil &A, const Block7Consts &C,
+                         double omega, const void *b, const void *xin,
+                         void *xout, bool bwd, Workspace &ws,
+                         const SweepPlan &plan, hipStream_t s);
+
 // bytes of one boundary record: the value and the launch epoch
 inline size_t c27_record_bytes(m2s_dtype t) { return t == M2S_F64 ? 16 : 8; }
 

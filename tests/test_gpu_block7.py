@@ -44,16 +44,15 @@ def test_ssor_parity(m, shape, direction):
     assert rel_inf(host(xg), ref) <= 1e-13
 
 
-@pytest.mark.parametrize("bk", ["1", "3"])
-def test_ssor_slab_thickness_bitwise(m, bk, monkeypatch):
+def test_ssor_tile_height_bitwise(m, monkeypatch):
     shape = (11, 9, 10)
     B = inputs.block7_blocks(4)
     A = m.block7(shape, B)
     b = dev(inputs.standard_normal(4, shape + (5,)))
     x0 = inputs.standard_normal(5, shape + (5,))
     outs = []
-    for planes in (bk, "2"):
-        monkeypatch.setenv("M2S_SLAB_PLANES", planes)
+    for nw in ("1", "2"):
+        monkeypatch.setenv("M2S_B7_WAVES", nw)
         xg = dev(x0)
         m.ssor_sweep(A, b, xg, 1.2, "sym")
         outs.append(host(xg))

@@ -93,32 +93,27 @@ def model_schedule(shape, plan, c27):
     return step, slab, D, G, Tfull
 
 
-@pytest.mark.parametrize("kind,shape", [
-    ("v7", (9, 7, 6)), ("v7", (6, 5, 12)), ("b7", (7, 4, 5)),
-])
+@pytest.mark.parametrize("shape", [(9, 7, 6), (6, 5, 12), (7, 4, 5)])
 @pytest.mark.parametrize("bk", [1, 2, 3, 0])
-def test_gpu_schedule_satisfies_all_dependences(kind, shape, bk, monkeypatch):
-    """Slab schedule of the 7-point sweeps (VAR7, BLOCK7)."""
+def test_gpu_schedule_satisfies_all_dependences(shape, bk, monkeypatch):
+    """Slab schedule of the VAR7 sweep."""
+    import torch
     import paper_2204_13304_amd as m
+    from paper_2204_13304_amd import _lib as L
     if bk:
         monkeypatch.setenv("M2S_SLAB_PLANES", str(bk))
     nz, ny, nx = shape
-    if kind == "v7":
-        import torch
-        A = m.Stencil.__new__(m.Stencil)
-        A.kind, A.shape, A.dtype = 1, shape, torch.float64
-        A.diag = A.off = 0.0
-        A.blocks = None
-        # faces are only read by the kernels; planning needs non-null
-        # pointers, so fake addresses are enough for this host-only call
-        from paper_2204_13304_amd import _lib as L
-        s = L.StencilC()
-        s.kind, s.dtype = 1, 0
-        s.ext = L.Extent(nx, ny, nz)
-        s.kx = s.ky = s.kz = 8
-        A._c = s
-    else:
-        A = m.block7(shape, np.eye(5)[None].repeat(7, 0) * 10)
+    A = m.Stencil.__new__(m.Stencil)
+    A.kind, A.shape, A.dtype = 1, shape, torch.float64
+    A.diag = A.off = 0.0
+    A.blocks = None
+    # faces are only read by the kernels; planning needs non-null pointers,
+    # so fake addresses are enough for this host-only call
+    s = L.StencilC()
+    s.kind, s.dtype = 1, 0
+    s.ext = L.Extent(nx, ny, nz)
+    s.kx = s.ky = s.kz = 8
+    A._c = s
     plan = m.plan_sweep(A)
     step, slab, D, G, Tfull = model_schedule(shape, plan, False)
     offs = lower_offsets_7()
@@ -370,3 +365,172 @@ def test_c27_plan_matches_tile_model(shape, monkeypatch):
         # nw compute + nw memory wavefronts + 1 poll wavefront
         assert p["threads"] == 64 * (2 * nw + 1)
         assert p["nslabs"] == len(c27_tile_list(shape, 4 * nw))
+
+
+# ---------------------------------------------------------------------------
+# Model of the tiled block-SSOR sweep kernel (7-point, 5 components): tiles
+# of 16 j by 4 nw k, rings of 8 columns, 4-column windows staged by an x and
+# a b memory wavefront per compute wavefront, and the poll wavefront.  As
+# above, but a wavefront that reads and writes one slot in one step does all
+# its reads first (the kernel orders them so), so only slots touched by two
+# different wavefronts in one step are races.
+# ---------------------------------------------------------------------------
+B7_TJ, B7_W, B7_POLL, B7_PRE = 16, 8, 4, 16
+
+
+def simulate_b7_tiles(shape, nw, zero_start=False):
+    nz, ny, nx = shape
+    KT = 4 * nw
+    njt = -(-ny // B7_TJ)
+    nbands = -(-nz // KT)
+    ticket = {(jt, vt): vt * njt + jt for vt in range(nbands)
+              for jt in range(njt)}
+    stored = {}
+
+    def valid(j, k):
+        return 0 <= j < ny and 0 <= k < nz
+
+    def old(j, k, c):
+        if not valid(j, k) or not 0 <= c < nx or zero_start:
+            return 0
+        return ("old", j, k, c)
+
+    for vt in range(nbands):
+        for jt in range(njt):
+            j0, k0 = B7_TJ * jt, KT * vt
+            T0 = j0 + k0
+            T_start = T0 - 1 - B7_PRE
+            T_lastc = T0 + (B7_TJ - 1) + (KT - 1) + nx - 1
+            nblk = (T_lastc + 5 - T_start + 15) // 16
+            xr, rr = {}, {}
+
+            def xs(kq, jq, c):
+                return ("x", (kq + 1, jq + 1), c % B7_W)
+
+            for step in range(16 * nblk):
+                T = T_start + step
+                p4 = step % 4
+                writes, reads = [], []
+                for m in range(nw):
+                    kk = 4 * m + p4
+                    wx, wb = nw + m, 2 * nw + m
+                    for e in range(320):
+                        jj, cq = e // 20, (e % 20) // 5
+                        j, k = j0 + jj, k0 + kk
+                        f = T - (j + k)
+                        cs, cx, cr = f - 4 + cq, f + 2 + cq, f + 1 + cq
+                        if valid(j, k) and 0 <= cs < nx:
+                            reads.append((xs(kk, jj, cs), wx,
+                                          ("new", j, k, cs)))
+                            stored[(k, j, cs)] = stored.get((k, j, cs), 0) + 1
+                        vx = 0 if T - 4 < T_start else old(j, k, cx)
+                        writes.append((xs(kk, jj, cx), vx, wx))
+                        vr = (0 if T - 4 < T_start or not valid(j, k) or
+                              not 0 <= cr < nx else ("r", j, k, cr))
+                        writes.append((("r", (kk, jj), cr % B7_W), vr, wb))
+                    for e in range(128):
+                        isa = e < 20
+                        if not (isa or (m == nw - 1 and e < 100)):
+                            continue
+                        jj = 16 if isa else 4 * p4 + (e - 20) // 20
+                        o = e if isa else (e - 20) % 20
+                        kq = kk if isa else KT
+                        j, k = j0 + jj, k0 + kq
+                        cx = T - (j + k) + 2 + o // 5
+                        vh = 0 if T - 4 < T_start else old(j, k, cx)
+                        writes.append((xs(kq, jj, cx), vh, wb))
+                wp = 3 * nw
+                for e in range(5 * (KT + 16)):
+                    h = e // 5
+                    left = h < KT
+                    jj, kk = (-1, h) if left else (h - KT, -1)
+                    prod = (jt - 1, vt) if left else (jt, vt - 1)
+                    ent = h if left else (KT + jj if jj < 15 else KT - 1)
+                    j, k = j0 + jj, k0 + kk
+                    c = T - (j + k)
+                    if not (valid(j, k) and c >= 0):
+                        continue
+                    if c < nx:
+                        assert T - B7_POLL >= T_start
+                        assert ticket[prod] < ticket[(jt, vt)]
+                        jp, kp = j - B7_TJ * prod[0], k - KT * prod[1]
+                        pe = (kp if jp == 15 else
+                              (KT + jp if kp == KT - 1 else -1))
+                        assert pe == ent, (pe, ent)
+                        v = ("new", j, k, c)
+                    else:
+                        v = 0
+                    writes.append((xs(kk, jj, c), v, wp))
+                for w in range(nw):
+                    for lane in range(64):
+                        jj, kk = lane & 15, 4 * w + (lane >> 4)
+                        j, k = j0 + jj, k0 + kk
+                        if not valid(j, k):
+                            continue
+                        f = T - (j + k)
+                        if not 0 <= f < nx:
+                            continue
+                        # neighbours that exist (has[]), own old at f, f+1
+                        nb = [((jj - 1, kk), j - 1 >= 0, True),
+                              ((jj, kk - 1), k - 1 >= 0, True),
+                              ((jj + 1, kk), j + 1 < ny, False),
+                              ((jj, kk + 1), k + 1 < nz, False)]
+                        for (jq, kq), ex, lower in nb:
+                            if ex:
+                                jn, kn = j0 + jq, k0 + kq
+                                e_ = (("new", jn, kn, f) if lower
+                                      else old(jn, kn, f))
+                                reads.append((xs(kq, jq, f), w, e_))
+                        reads.append((xs(kk, jj, f), w, old(j, k, f)))
+                        if f + 1 < nx:
+                            reads.append((xs(kk, jj, f + 1), w,
+                                          old(j, k, f + 1)))
+                        reads.append((("r", (kk, jj), f % B7_W), w,
+                                      ("r", j, k, f)))
+                        writes.append((xs(kk, jj, f), ("new", j, k, f), w))
+                wsl = {}
+                for slot, v, w in writes:
+                    prev = wsl.get(slot)
+                    assert prev is None or prev[1] == w, ("write race", slot)
+                    wsl[slot] = (v, w)
+                for slot, w, e_ in reads:
+                    if slot in wsl:
+                        assert wsl[slot][1] == w, ("read/write race", slot, T)
+                    mem = xr if slot[0] == "x" else rr
+                    got = mem.get(slot[1:], 0)
+                    assert got == e_, (T, slot, got, e_)
+                for slot, (v, w) in wsl.items():
+                    (xr if slot[0] == "x" else rr)[slot[1:]] = v
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                # five lanes (components) store each point's entry
+                assert stored.get((k, j, i)) == 5, ("store", (k, j, i))
+
+
+@pytest.mark.parametrize("shape", [(9, 7, 6), (5, 20, 11), (13, 17, 3),
+                                   (1, 1, 1), (4, 33, 5)])
+@pytest.mark.parametrize("nw", [1, 2])
+def test_b7_tile_model(shape, nw):
+    simulate_b7_tiles(shape, nw)
+
+
+def test_b7_tile_model_zero_start():
+    simulate_b7_tiles((6, 9, 5), 1, zero_start=True)
+
+
+def b7_tile_count(shape, nw):
+    nz, ny, nx = shape
+    return -(-ny // B7_TJ) * -(-nz // (4 * nw))
+
+
+@pytest.mark.parametrize("shape", [(9, 7, 6), (16, 16, 16), (13, 40, 9)])
+def test_b7_plan_matches_tile_model(shape, monkeypatch):
+    import paper_2204_13304_amd as m
+    for nw in (1, 2):
+        monkeypatch.setenv("M2S_B7_WAVES", str(nw))
+        p = m.plan_sweep(m.block7(shape, np.eye(5)[None].repeat(7, 0) * 10))
+        assert p["slab_planes"] == 4 * nw
+        # nw compute + 2 nw memory wavefronts + 1 poll wavefront
+        assert p["threads"] == 64 * (3 * nw + 1)
+        assert p["nslabs"] == b7_tile_count(shape, nw)
