@@ -21,10 +21,17 @@ Also reported on the same line:
   spmv              the 27-point SpMV kernel (16 B per point) likewise;
   time_to_solution  FP64 MG-PCG and mixed MG-PCG (V-cycle in FP32, CG in
                     FP64) to relative residual 1e-9 from x0 = 0;
-  cpu_baseline      the CPU oracle (one thread) on one MG-PCG iteration.
+  cpu_baseline      the CPU oracle (one thread) on one MG-PCG iteration;
+  workloads         the other two workloads of the hot path:
+                    block SSOR on the 162^3 x 5 BLOCK7 operator (20
+                    iterations, omega 1.2, b = A*1, x0 = 0; 120 B per point
+                    per half-sweep) and the differentiable VAR7 solve at
+                    128^3 (MG-PCG to 1e-10, then the adjoint solve and the
+                    face gradient of 0.5*|u - u_t|^2).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 2]
     python bench.py --roofline-only      (kernel loops only, for profiling)
+    python bench.py --workloads-only     (the block SSOR and VAR7 runs only)
 """
 from __future__ import annotations
 
@@ -74,6 +81,10 @@ def parse():
                     help="skip the CPU-oracle baseline")
     ap.add_argument("--no-tts", action="store_true",
                     help="skip the time-to-solution runs")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the block SSOR and VAR7 workloads")
+    ap.add_argument("--workloads-only", action="store_true",
+                    help="only the block SSOR and VAR7 workloads")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the kernel loops and a copy calibration")
     return ap.parse_args()
@@ -96,6 +107,79 @@ def flops_per_iteration(n, levels):
     f += 3 * 2 * n ** 3                  # three dot products
     f += 3 * 2 * n ** 3                  # x, r, p updates
     return f
+
+
+def extra_workloads(torch, m, inputs, dev, reps):
+    """Block SSOR (162^3 x 5) and the VAR7 solve with its gradient (128^3)."""
+    f64 = torch.float64
+    out = {}
+    n = 162
+    shape = (n, n, n)
+    A = m.block7(shape, inputs.block7_blocks(4))
+    ws = m.Workspace(A)
+    ones = torch.ones(shape + (5,), dtype=f64, device=dev)
+    b = m.spmv(A, ones)
+    x = torch.zeros_like(b)
+    m.ssor_sweep(A, b, x, 1.2, "sym", ws)  # warm
+    x.zero_()
+    iters = 20
+    ms = event_ms(torch, lambda: m.ssor_sweep(A, b, x, 1.2, "sym", ws), iters)
+    ws.check()
+    err = (x - 1.0).abs().max().item()
+    fwd = event_ms(torch, lambda: m.ssor_sweep(A, b, x, 1.2, "fwd", ws), reps)
+    bwd = event_ms(torch, lambda: m.ssor_sweep(A, b, x, 1.2, "bwd", ws), reps)
+    ws.check()
+    half = 0.5 * (fwd + bwd)
+    gbs = 120 * n ** 3 / (half * 1e-3) / 1e9
+    out["block_ssor"] = {
+        "workload": "block7 162^3 x 5, blocks seed 4, omega 1.2, b = A*1, "
+                    "x0 = 0, 20 iterations (forward + backward)",
+        "seconds_20_iterations": ms * iters * 1e-3,
+        "max_abs_err_vs_ones": err,
+        "half_sweep_ms": half, "fwd_ms": fwd, "bwd_ms": bwd,
+        "achieved": gbs, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+        "kernel": "b7_tile_kernel (fwd and bwd), 120 B/point"}
+    log(f"block SSOR 162^3x5: 20 iterations {ms * iters:.1f} ms, half-sweep "
+        f"{half:.3f} ms ({gbs:.0f} GB/s), |x - 1| {err:.2e}")
+    del A, ws, b, x, ones
+
+    n = 128
+    shape = (n, n, n)
+    P = inputs.var7_problem(5, shape)
+    kx, ky, kz, f = (torch.from_numpy(P[k]).to(dev).requires_grad_(True)
+                     for k in ("kx", "ky", "kz", "f"))
+    ut = torch.from_numpy(P["u_t"]).to(dev)
+    A7 = m.var7(kx.detach(), ky.detach(), kz.detach())
+    ws7 = m.Workspace(A7)
+    r = f.detach().clone()
+    x0 = torch.from_numpy(inputs.standard_normal(12, shape)).to(dev)
+    x1 = torch.empty_like(x0)
+    m.symgs_oop(A7, r, x0, x1, "fwd", ws7)
+    sw = event_ms(torch, lambda: m.symgs_oop(A7, r, x0, x1, "fwd", ws7), reps)
+    ws7.check()
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    u = m.solve(kx, ky, kz, f, levels=4, rtol=1e-10, max_iter=1000)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    loss = 0.5 * ((u - ut) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    tc = time.perf_counter()
+    info = getattr(u.grad_fn, "info", {}) or {}
+    out["var7_grad"] = {
+        "workload": "var7 128^3 (faces exp(N(0, 0.5^2)), seed 5), 4-level "
+                    "MG-PCG to 1e-10, loss 0.5*|u - u_t|^2, adjoint solve "
+                    "and face gradient",
+        "forward_seconds": tb - ta, "backward_seconds": tc - tb,
+        "iterations": info.get("iters"),
+        "true_rel_res": info.get("true_rel_res"),
+        "sweep_fwd_ms": sw,
+        "sweep_achieved": 48 * n ** 3 / (sw * 1e-3) / 1e9,
+        "sweep_unit": "GB/s (48 B/point: r, x_old, x_new, three face arrays)"}
+    log(f"var7 128^3: solve {tb - ta:.3f} s ({info.get('iters')} its), "
+        f"gradient {tc - tb:.3f} s, sweep {sw:.3f} ms")
+    return out
 
 
 def log(msg):
@@ -171,6 +255,11 @@ def main():
     n, L = args.n, args.levels
     shape = (n, n, n)
 
+    if args.workloads_only:
+        print(json.dumps({"workloads": extra_workloads(torch, m, inputs, dev,
+                                                       args.reps)}))
+        return 0
+
     log(f"roofline loops at {n}^3, {args.reps} launches each")
     rl = roofline_loops(torch, m, inputs, n, args.reps, dev)
     log(f"sweep fwd {rl['fwd_ms']:.3f} ms bwd {rl['bwd_ms']:.3f} ms "
@@ -241,6 +330,10 @@ def main():
                    res["mixed"]["seconds"],
                    mixed_vs_fp64_solution_rel_err=err)
 
+    extra = None
+    if not args.no_extra:
+        extra = extra_workloads(torch, m, inputs, dev, args.reps)
+
     cpu = None
     if not args.no_cpu:
         try:
@@ -289,6 +382,7 @@ def main():
         "sweep_fp32": {"avg_ms": rl["fwd32_ms"], "achieved": rl["fwd32_gbs"],
                        "unit": "GB/s"},
         "time_to_solution": tts,
+        "workloads": extra,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
