@@ -275,11 +275,12 @@ m2s_status m2s_convert(const void *src, m2s_dtype src_t, void *dst,
  *   consecutive u = j + k by slab_planes consecutive k (4 per wavefront),
  *   one lane per row; nslabs = number of tiles holding a grid row, taken in
  *   lexicographic (k-tile, u-tile) order; steps = steps of a full tile.
- * M2S_VAR7, M2S_BLOCK7_5: slabs of slab_planes whole planes, row_slots
- *   threads per plane; nslabs = number of slabs; steps = local steps of a
- *   full slab.
- * threads = workgroup size; publish_every = progress-publication interval
- * of the slab schedule.
+ * M2S_VAR7, M2S_BLOCK7_5: tiles of row_slots = 16 consecutive j by
+ *   slab_planes consecutive k, one lane per row; nslabs = number of tiles,
+ *   taken in lexicographic (k-tile, j-tile) order; steps = steps of a full
+ *   tile.
+ * threads = workgroup size; publish_every = 1 (tiles hand over their
+ * boundary rows every step).
  * --------------------------------------------------------------------- */
 typedef struct {
     int32_t slab_planes, nslabs, row_slots, lag_row, lag_plane, steps;

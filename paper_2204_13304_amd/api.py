@@ -122,6 +122,9 @@ class Workspace:
         L.check(lib.m2s_workspace_create(A.ref(), C.byref(h)),
                 "m2s_workspace_create")
         self._h = h
+        # bound now: module globals may already be gone when the object is
+        # collected at interpreter exit
+        self._destroy = lib.m2s_workspace_destroy
 
     @property
     def handle(self):
@@ -133,7 +136,7 @@ class Workspace:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            L.load().m2s_workspace_destroy(h)
+            self._destroy(h)
             self._h = None
 
 
@@ -226,6 +229,7 @@ class MG:
         L.check(lib.m2s_mg_create(A.ref(), int(levels), _DT[prec],
                                   C.byref(h)), "m2s_mg_create")
         self._h = h
+        self._destroy = lib.m2s_mg_destroy
         self.levels = levels
         self.prec = prec
 
@@ -245,7 +249,7 @@ class MG:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            L.load().m2s_mg_destroy(h)
+            self._destroy(h)
             self._h = None
 
 

@@ -19,7 +19,6 @@ hipError_t launch_sweep_sequential_b7(const m2s_stencil &A,
                                       const Block7Consts &b7, double omega,
                                       const void *b, void *x, bool bwd,
                                       hipStream_t s);
-int sweep_max_blocks_per_cu(m2s_kind kind, m2s_dtype t, int threads);
 
 // LU with partial pivoting of the 5x5 centre block (row-major), host side.
 hipError_t fill_block7_consts(const double *blocks, Block7Consts &C)
@@ -57,7 +56,6 @@ struct m2s_workspace : public Workspace {};
 
 namespace {
 
-constexpr int kMaxThreads = 1024;
 
 int env_int(const char *name, int dflt)
 {
@@ -115,19 +113,15 @@ m2s_status hip_status(hipError_t e)
         if (e_ != hipSuccess) return M2S_ERR_HIP;       \
     } while (0)
 
-// The wavefront schedule.  Row j of local plane kk of a slab processes
-// column i at local step i + LJ*j + LK*kk; a thread owns the rows
-// j = s, s+R, s+2R, ... of one plane, which never overlap in time because
-// LJ*R >= nx.
+// The wavefront schedule: tiles of 16 rows by 4 * nw planes, one lane per
+// row; point (i, j, k) runs at step i + lag_row*j + lag_plane*k within its
+// tile (the hyperplane of Sec. 6.1.3; rows u = j + k for 27 points).
 m2s_status make_plan(const m2s_stencil &A, SweepPlan &P, bool with_grid)
 {
     const int nx = A.ext.nx, ny = A.ext.ny, nz = A.ext.nz;
     const bool c27 = A.kind == M2S_CONST27;
     P.lag_row = c27 ? 2 : 1;
     P.lag_plane = c27 ? 4 : 1;
-    P.halo_x = c27 ? 1 : 0;
-    P.halo_y = c27 ? 1 : 0;
-    int R, bk = env_int("M2S_SLAB_PLANES", 0);
     if (c27) {
         // tiles of 16 u = j + k rows by 4 * nw planes, one lane per row;
         // buffer loads address a vector with 32-bit byte offsets
@@ -162,6 +156,38 @@ m2s_status make_plan(const m2s_stencil &A, SweepPlan &P, bool with_grid)
             P.grid = std::max(1, std::min(P.nslabs, cus * per_cu));
         }
         return M2S_OK;
+    } else if (A.kind == M2S_VAR7) {
+        // rectangular tiles of 16 j by 4 * nw k, one lane per row; buffer
+        // loads address x, r and the face arrays with 32-bit byte offsets
+        const int64_t es = elem_size(A);
+        if ((int64_t)nz * ny * (nx + 1) * es >= ((int64_t)1 << 31) ||
+            (int64_t)nz * (ny + 1) * nx * es >= ((int64_t)1 << 31) ||
+            (int64_t)(nz + 1) * ny * nx * es >= ((int64_t)1 << 31))
+            return M2S_ERR_SHAPE;
+        // one compute wavefront (4 planes) per tile measured fastest: the
+        // tile's step is short, so more tiles in flight beat fewer crossings
+        int nw = env_int("M2S_V7_WAVES", 1);
+        if (nw != 1 && nw != 2 && nw != 4) nw = 1;
+        const V7Layout L = v7_layout(Grid{nx, ny, nz}, nw);
+        if (L.bnd_elems * (int64_t)c27_record_bytes(A.dtype) >=
+            ((int64_t)1 << 31))
+            return M2S_ERR_SHAPE;
+        P.row_slots = 16;
+        P.slab_planes = L.kt;
+        P.nslabs = L.ntiles;
+        P.threads = v7_threads(nw);
+        P.publish_every = 1;
+        P.grid = 0;
+        if (with_grid) {
+            int dev = 0, cus = 0;
+            if (hipGetDevice(&dev) != hipSuccess) return M2S_ERR_HIP;
+            if (hipDeviceGetAttribute(&cus,
+                                      hipDeviceAttributeMultiprocessorCount,
+                                      dev) != hipSuccess)
+                return M2S_ERR_HIP;
+            P.grid = std::max(1, std::min(P.nslabs, cus));
+        }
+        return M2S_OK;
     } else if (A.kind == M2S_BLOCK7_5) {
         // rectangular tiles of 16 j by 4 * nw k, one lane per row
         if ((int64_t)nx * ny * nz * 40 >= ((int64_t)1 << 31))
@@ -190,38 +216,8 @@ m2s_status make_plan(const m2s_stencil &A, SweepPlan &P, bool with_grid)
             P.grid = std::max(1, std::min(P.nslabs, cus));
         }
         return M2S_OK;
-    } else {
-        R = (nx + P.lag_row - 1) / P.lag_row;
-        if (R > ny) R = ny;
-        if (R > kMaxThreads) return M2S_ERR_SHAPE;
-        if (bk <= 0) {
-            // enough rows per workgroup to fill a CU without serialising too
-            // much of the plane chain on one workgroup
-            bk = std::max(1, std::min(8, 512 / R));
-        }
-        if (bk * R > kMaxThreads) bk = kMaxThreads / R;
     }
-    P.row_slots = R;
-    if (bk > nz) bk = nz;
-    if (bk < 1) bk = 1;
-    P.slab_planes = bk;
-    P.nslabs = (nz + bk - 1) / bk;
-    P.threads = ((bk * R + 63) / 64) * 64;
-    P.publish_every = env_int("M2S_PUBLISH_EVERY", 4);
-    if (P.publish_every < 1) P.publish_every = 1;
-    P.grid = 0;
-    if (with_grid) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess) return M2S_ERR_HIP;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
-                                  dev) != hipSuccess)
-            return M2S_ERR_HIP;
-        int per_cu = sweep_max_blocks_per_cu(A.kind, A.dtype, P.threads);
-        int64_t cap = (int64_t)cus * per_cu;
-        P.grid = (int)std::min<int64_t>(P.nslabs, cap);
-        if (P.grid < 1) P.grid = 1;
-    }
-    return M2S_OK;
+    return M2S_ERR_UNSUPPORTED;
 }
 
 m2s_status check_ws(const m2s_stencil &A, const m2s_workspace *ws)
@@ -256,6 +252,13 @@ m2s_status ensure_tiles(m2s_workspace *ws, int nw)
         ws->tile_ntiles = (int)tiles.size();
         ws->tile_nutb = L.nutb;
         ws->tile_ns = L.ns;
+    } else if (ws->kind == M2S_VAR7) {
+        const V7Layout L = v7_layout(ws->g, nw);
+        n = std::max<int64_t>(L.bnd_elems, 1);
+        rb = c27_record_bytes(ws->dtype);
+        ws->tile_ntiles = L.ntiles;
+        ws->tile_nutb = L.njt;
+        ws->tile_ns = L.ns;
     } else {
         const B7Layout L = b7_layout(ws->g, nw);
         n = std::max<int64_t>(L.bnd_elems, 1);
@@ -288,10 +291,7 @@ m2s_status half_sweep(const m2s_stencil &A, const Block7Consts *b7,
     SweepPlan P{};
     m2s_status st = make_plan(A, P, true);
     if (st != M2S_OK) return st;
-    const bool tiled = A.kind == M2S_CONST27 || A.kind == M2S_BLOCK7_5;
-    if (!tiled && P.nslabs > ws->nflags) return M2S_ERR_SHAPE;
-    if (tiled && (st = ensure_tiles(ws, P.slab_planes / 4)) != M2S_OK)
-        return st;
+    if ((st = ensure_tiles(ws, P.slab_planes / 4)) != M2S_OK) return st;
     return hip_status(launch_sweep(A, b7, omega, r, xin, xout, bwd, zero_init,
                                    *ws, P, s));
 }
@@ -335,11 +335,8 @@ m2s_status m2s_plan_sweep(const m2s_stencil *A, m2s_sweep_plan *plan)
     if (A->kind == M2S_CONST27)  // u = j + k: T = i + 2u + 2k
         plan->steps = A->ext.nx + 2 * (P.row_slots - 1) +
                       2 * (P.slab_planes - 1);
-    else if (A->kind == M2S_BLOCK7_5)  // T = i + j + k within a tile
+    else  // VAR7, BLOCK7: T = i + j + k within a tile
         plan->steps = A->ext.nx + (P.row_slots - 1) + (P.slab_planes - 1);
-    else
-        plan->steps = A->ext.nx + P.lag_row * (A->ext.ny - 1) +
-                      P.lag_plane * (P.slab_planes - 1);
     plan->threads = P.threads;
     plan->publish_every = P.publish_every;
     return M2S_OK;
@@ -358,15 +355,12 @@ m2s_status m2s_workspace_create(const m2s_stencil *A, m2s_workspace **out)
     ws->dtype = A->dtype;
     ws->g = Grid{A->ext.nx, A->ext.ny, A->ext.nz};
     if (hipGetDevice(&ws->dev) != hipSuccess) { delete ws; return M2S_ERR_HIP; }
-    ws->nflags = A->ext.nz;
     const size_t vb = (size_t)npoints(*A) * elem_size(*A);
-    bool ok = hipMalloc(&ws->flags, sizeof(uint64_t) * ws->nflags) ==
-                  hipSuccess &&
-              hipMalloc(&ws->ticket, sizeof(uint64_t)) == hipSuccess &&
+    bool ok = hipMalloc(&ws->ticket, sizeof(uint64_t)) == hipSuccess &&
               hipMalloc(&ws->err, sizeof(int)) == hipSuccess &&
               hipMalloc(&ws->scratch, vb) == hipSuccess &&
               hipMalloc(&ws->scratch2, vb) == hipSuccess;
-    if (ok && (A->kind == M2S_CONST27 || A->kind == M2S_BLOCK7_5)) {
+    if (ok) {
         SweepPlan P{};
         const m2s_status pst = make_plan(*A, P, false);
         if (pst != M2S_OK) {
@@ -375,9 +369,7 @@ m2s_status m2s_workspace_create(const m2s_stencil *A, m2s_workspace **out)
         }
         ok = ensure_tiles(ws, P.slab_planes / 4) == M2S_OK;
     }
-    ok = ok && hipMemset(ws->flags, 0, sizeof(uint64_t) * ws->nflags) ==
-                   hipSuccess &&
-         hipMemset(ws->ticket, 0, sizeof(uint64_t)) == hipSuccess &&
+    ok = ok && hipMemset(ws->ticket, 0, sizeof(uint64_t)) == hipSuccess &&
          hipMemset(ws->err, 0, sizeof(int)) == hipSuccess &&
          hipDeviceSynchronize() == hipSuccess;
     if (!ok) {
@@ -392,7 +384,6 @@ void m2s_workspace_destroy(m2s_workspace *ws)
 {
     if (!ws) return;
     (void)hipDeviceSynchronize();
-    if (ws->flags) (void)hipFree(ws->flags);
     if (ws->ticket) (void)hipFree(ws->ticket);
     if (ws->err) (void)hipFree(ws->err);
     if (ws->scratch) (void)hipFree(ws->scratch);

@@ -72,16 +72,14 @@ struct Block7Consts {
 
 // Wavefront schedule of one sweep (see the sweep kernel for its meaning).
 struct SweepPlan {
-    int slab_planes;  // planes per slab (Bk)
-    int nslabs;
-    int row_slots;    // R: threads per plane in a workgroup
-    int lag_row;      // LJ
-    int lag_plane;    // LK
-    int halo_x;       // largest x offset among lower neighbours in plane k-1
-    int halo_y;       // largest y offset among lower neighbours in plane k-1
+    int slab_planes;  // planes per tile (4 per compute wavefront)
+    int nslabs;       // tiles
+    int row_slots;    // rows per tile and plane
+    int lag_row;      // step weight of a row (2 for 27 points: T = i+2u+2k)
+    int lag_plane;    // step weight of a plane
     int threads;      // workgroup size
-    int publish_every;
-    int grid;         // workgroups launched (<= nslabs)
+    int publish_every;  // boundary records are written every step: 1
+    int grid;         // workgroups launched (<= tiles)
 };
 
 // x_i = (r_i - off * (S + x_new(i-1))) / diag, evaluated as
@@ -97,6 +95,23 @@ __device__ __forceinline__ T c27_combine(T r, T B, T Dp, T xn_prev, T off,
     const T S = B + Dp;
     const T t1 = fma(-off, xn_prev, r);
     return fma(-off, S, t1) * inv_diag;
+}
+
+// VAR7 point update x_p = (r_p + sum_d k_d x_q) / (sum_d k_d) over the six
+// faces in real orientation (m: the face towards -x, p: towards +x, ...);
+// neighbours outside the grid enter as 0.  The sequential and the tiled
+// sweep kernels both call this function, so their results agree bitwise.
+template <typename T>
+__device__ __forceinline__ T v7_combine(T r, T vmx, T vpx, T vmy, T vpy,
+                                        T vmz, T vpz, T kxm, T kxp, T kym,
+                                        T kyp, T kzm, T kzp)
+{
+    const T s1 = fma(kxm, vmx, kxp * vpx);
+    const T s2 = fma(kym, vmy, kyp * vpy);
+    const T s3 = fma(kzm, vmz, kzp * vpz);
+    const T S = (s1 + s2) + s3;
+    const T d = ((kxm + kxp) + (kym + kyp)) + (kzm + kzp);
+    return (r + S) / d;
 }
 
 // One block-SSOR point (the NPB-LU-shaped BLOCK7x5 operator, Sec. 7.1):
@@ -167,12 +182,11 @@ struct Workspace {
     m2s_dtype dtype;
     Grid g;
     int dev;
-    uint64_t *flags;    // nslabs_max progress flags, epoch-tagged
     uint64_t *ticket;   // ticket counter (monotone)
     int *err;           // device error latch
     void *scratch;      // one vector of the stencil's size
     void *scratch2;     // second vector (adjoint chains)
-    void *bnd;          // 27-point sweep: tile boundary store (records)
+    void *bnd;          // tiled sweeps: tile boundary store (records)
     int64_t bnd_elems;  // records
     int tile_nw;        // compute wavefronts per tile of the layout
     int tile_ntiles;
@@ -182,7 +196,6 @@ struct Workspace {
     void *b7c;          // block SSOR: device copy of the block constants
     Block7Consts b7c_host;
     bool b7c_valid;
-    int64_t nflags;
     uint32_t epoch;
     uint64_t ticket_base;
 };
@@ -251,6 +264,17 @@ hipError_t launch_sweep7(const m2s_stencil &A, const Block7Consts &C,
                          double omega, const void *b, const void *xin,
                          void *xout, bool bwd, Workspace &ws,
                          const SweepPlan &plan, hipStream_t s);
+
+// Tiling of the VAR7 sweep (k_sweep7v.hip): the same rectangular tiles,
+// one boundary record per row.
+using V7Layout = B7Layout;
+V7Layout v7_layout(Grid g, int nw);
+size_t v7_lds_bytes(int nw, m2s_dtype t);
+int v7_threads(int nw);  // nw compute + nw memory + 1 poll wavefronts
+hipError_t launch_sweep7v(const m2s_stencil &A, const void *r,
+                          const void *xin, void *xout, bool bwd,
+                          Workspace &ws, const SweepPlan &plan,
+                          hipStream_t s);
 
 // bytes of one boundary record: the value and the launch epoch
 inline size_t c27_record_bytes(m2s_dtype t) { return t == M2S_F64 ? 16 : 8; }

@@ -1,6 +1,6 @@
 """GPU parity of the BLOCK7x5 SpMV and the block SSOR half-sweeps (NPB-LU
-shaped, omega = 1.2) against the oracle, bitwise agreement between slab
-thicknesses, and the 162^3 x 5 configuration point by point."""
+shaped, omega = 1.2) against the oracle, bitwise agreement between tile
+heights, and the 162^3 x 5 configuration point by point."""
 import numpy as np
 import pytest
 import torch

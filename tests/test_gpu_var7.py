@@ -56,6 +56,57 @@ def test_symgs_var7(m, shape, direction):
     assert np.array_equal(out, host(xs))
 
 
+@pytest.mark.parametrize("direction", ["fwd", "bwd"])
+def test_symgs_var7_tiles_bitwise(m, direction, monkeypatch):
+    """Several tiles along j and k with ragged tails, every tile height:
+    parity with the oracle and bitwise equality with the sequential
+    kernel."""
+    shape = (21, 37, 19)
+    pr = inputs.var7_problem(24, shape)
+    A = _A(m, pr)
+    r = inputs.standard_normal(5, shape)
+    x0 = inputs.standard_normal(6, shape)
+    ref = oracle.symgs_var7(r, x0, pr["kx"], pr["ky"], pr["kz"], direction)
+    xs = dev(x0)
+    m.symgs_sequential(A, dev(r), xs, direction)
+    seq = host(xs)
+    for nw in ("1", "2", "4"):
+        banner(f"var7 tiles nw={nw} {direction} {shape}")
+        monkeypatch.setenv("M2S_V7_WAVES", nw)
+        xg = dev(x0)
+        m.symgs(A, dev(r), xg, direction, m.Workspace(A))
+        out = host(xg)
+        assert rel_inf(out, ref) <= 1e-13
+        assert np.array_equal(out, seq)
+
+
+def test_var7_float32_tiles_bitwise(m):
+    shape = (19, 35, 17)
+    pr = inputs.var7_problem(25, shape)
+    A = _A(m, pr, torch.float32)
+    r = dev(inputs.standard_normal(7, shape), torch.float32)
+    x0 = dev(inputs.standard_normal(8, shape), torch.float32)
+    xg, xs = x0.clone(), x0.clone()
+    m.symgs(A, r, xg, "sym")
+    m.symgs_sequential(A, r, xs, "sym")
+    assert torch.equal(xg, xs)
+
+
+def test_var7_full_size_128(m):
+    """The 128^3 workload of the differentiable solve: one forward and one
+    backward half-sweep, bitwise against the sequential kernel."""
+    shape = (128, 128, 128)
+    banner(f"var7 full size {shape}")
+    pr = inputs.var7_problem(5, shape)
+    A = _A(m, pr)
+    r = dev(inputs.standard_normal(9, shape))
+    x0 = dev(inputs.standard_normal(10, shape))
+    xg, xs = x0.clone(), x0.clone()
+    m.symgs(A, r, xg, "sym")
+    m.symgs_sequential(A, r, xs, "sym")
+    assert torch.equal(xg, xs)
+
+
 def test_var7_float32(m):
     shape = (12, 10, 14)
     pr = inputs.var7_problem(23, shape)

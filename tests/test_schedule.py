@@ -1,8 +1,10 @@
 """CPU checks of the wavefront schedule (no GPU): the hyperplane legality
-criterion of Sec. 6.1.3 (pinned to the paper's 2-D example), and a brute-
-force model of the slab/row-slot schedule that libm2s.so plans
-(m2s_plan_sweep), checking that every dependence of the lexicographic sweep
-is satisfied by it."""
+criterion of Sec. 6.1.3 (pinned to the paper's 2-D example), and models of
+the three tiled sweep kernels (27-point, VAR7, block SSOR) that replay each
+kernel's index arithmetic step by step on symbolic values, checking that
+every read of the lexicographic sweep sees the right value, that no two
+wavefronts race on a slot, and that the tilings match what libm2s.so plans
+(m2s_plan_sweep)."""
 import itertools
 import json
 import os
@@ -61,81 +63,23 @@ def test_27_point_hyperplane_weights():
     assert legal((1, 1, 1), lower_offsets_7())
 
 
-# ---------------------------------------------------------------------------
-# Model of the GPU schedule (mirrors the sweep kernel's index arithmetic).
-# ---------------------------------------------------------------------------
-def model_schedule(shape, plan, c27):
-    nz, ny, nx = shape
-    Bk, R = plan["slab_planes"], plan["row_slots"]
-    LJ, LK = plan["lag_row"], plan["lag_plane"]
-    hx = hy = 1 if c27 else 0
-    D = 1 + hx + LJ * hy + LK * (Bk - 1)
-    G = plan["publish_every"]
-    step = np.empty(shape, dtype=np.int64)
-    slab = np.empty(shape, dtype=np.int64)
-    owner = {}
-    for k in range(nz):
-        K, kk = divmod(k, Bk)
-        for j in range(ny):
-            s = j % R
-            for i in range(nx):
-                t = i + LJ * j + LK * kk
-                # the kernel's inverse mapping must give back (i, j)
-                rel = t - LK * kk - LJ * s
-                m = 0 if R >= ny else rel // (LJ * R)
-                assert (rel - m * LJ * R, s + m * R) == (i, j)
-                key = (K, kk, s, t)
-                assert key not in owner, "two points on one thread and step"
-                owner[key] = (i, j, k)
-                step[k, j, i] = t
-                slab[k, j, i] = K
-    Tfull = nx + LJ * (ny - 1) + LK * (Bk - 1)
-    return step, slab, D, G, Tfull
-
-
-@pytest.mark.parametrize("shape", [(9, 7, 6), (6, 5, 12), (7, 4, 5)])
-@pytest.mark.parametrize("bk", [1, 2, 3, 0])
-def test_gpu_schedule_satisfies_all_dependences(shape, bk, monkeypatch):
-    """Slab schedule of the VAR7 sweep."""
+def _fake_var7(m, shape):
+    """A VAR7 stencil descriptor for host-only planning calls: faces are
+    only read by the kernels and planning needs non-null pointers, so fake
+    addresses are enough."""
     import torch
-    import paper_2204_13304_amd as m
     from paper_2204_13304_amd import _lib as L
-    if bk:
-        monkeypatch.setenv("M2S_SLAB_PLANES", str(bk))
     nz, ny, nx = shape
     A = m.Stencil.__new__(m.Stencil)
     A.kind, A.shape, A.dtype = 1, shape, torch.float64
     A.diag = A.off = 0.0
     A.blocks = None
-    # faces are only read by the kernels; planning needs non-null pointers,
-    # so fake addresses are enough for this host-only call
     s = L.StencilC()
     s.kind, s.dtype = 1, 0
     s.ext = L.Extent(nx, ny, nz)
     s.kx = s.ky = s.kz = 8
     A._c = s
-    plan = m.plan_sweep(A)
-    step, slab, D, G, Tfull = model_schedule(shape, plan, False)
-    offs = lower_offsets_7()
-    for k in range(nz):
-        for j in range(ny):
-            for i in range(nx):
-                t, K = step[k, j, i], slab[k, j, i]
-                for dk, dj, di in offs:
-                    a = (k - dk, j - dj, i - di)
-                    if not (0 <= a[0] < nz and 0 <= a[1] < ny and
-                            0 <= a[2] < nx):
-                        continue
-                    ta, Ka = step[a], slab[a]
-                    if Ka == K:
-                        assert ta < t, (a, (k, j, i))
-                    else:
-                        # producer slab must be exactly the previous one and
-                        # covered by the progress wait of the G-window
-                        assert Ka == K - 1
-                        t0 = t - t % G
-                        need = min(Tfull, t0 + G - 1 + D)
-                        assert ta < need, (a, (k, j, i), ta, need)
+    return A
 
 
 # ---------------------------------------------------------------------------
@@ -534,3 +478,184 @@ def test_b7_plan_matches_tile_model(shape, monkeypatch):
         # nw compute + 2 nw memory wavefronts + 1 poll wavefront
         assert p["threads"] == 64 * (3 * nw + 1)
         assert p["nslabs"] == b7_tile_count(shape, nw)
+
+
+# ---------------------------------------------------------------------------
+# Model of the tiled VAR7 sweep kernel: the block SSOR tiles with one value
+# per row and five staged arrays (x, r, x-faces, the y- and z-face below each
+# row in sweep order), the row j0 + 16 (x, y-faces) and the plane k0 + KT
+# (x, z-faces) as halo, one memory wavefront per compute wavefront.  Reads
+# of neighbours outside the grid must give exactly 0 (they are multiplied by
+# boundary faces), and every face read must give that face.
+# ---------------------------------------------------------------------------
+V7_TJ, V7_W, V7_POLL, V7_PRE = 16, 8, 4, 16
+
+
+def simulate_v7_tiles(shape, nw, zero_start=False):
+    nz, ny, nx = shape
+    KT = 4 * nw
+    njt = -(-ny // V7_TJ)
+    nbands = -(-nz // KT)
+    ticket = {(jt, vt): vt * njt + jt for vt in range(nbands)
+              for jt in range(njt)}
+    stored = {}
+
+    def valid(j, k):
+        return 0 <= j < ny and 0 <= k < nz
+
+    def old(j, k, c):
+        if not valid(j, k) or not 0 <= c < nx or zero_start:
+            return 0
+        return ("old", j, k, c)
+
+    def new(j, k, c):
+        return ("new", j, k, c) if valid(j, k) and 0 <= c < nx else 0
+
+    def arr(name, j, k, c):
+        ok = {"r": valid(j, k) and 0 <= c < nx,
+              "kx": valid(j, k) and 0 <= c <= nx,
+              "ky": 0 <= j <= ny and 0 <= k < nz and 0 <= c < nx,
+              "kz": 0 <= j < ny and 0 <= k <= nz and 0 <= c < nx}[name]
+        return (name, j, k, c) if ok else 0
+
+    for vt in range(nbands):
+        for jt in range(njt):
+            j0, k0 = V7_TJ * jt, KT * vt
+            T0 = j0 + k0
+            T_start = T0 - 1 - V7_PRE
+            T_lastc = T0 + (V7_TJ - 1) + (KT - 1) + nx - 1
+            nblk = (T_lastc + 5 - T_start + 15) // 16
+            mem = {}
+
+            for step in range(16 * nblk):
+                T = T_start + step
+                p4 = step % 4
+                writes, reads = [], []
+                for m in range(nw):
+                    kk = 4 * m + p4
+                    wm = nw + m
+                    for lane in range(64):
+                        jj, cq = lane >> 2, lane & 3
+                        j, k = j0 + jj, k0 + kk
+                        f = T - (j + k)
+                        cs = f - 4 + cq
+                        if valid(j, k) and 0 <= cs < nx:
+                            reads.append((("x", kk, jj, cs % V7_W), wm,
+                                          ("new", j, k, cs)))
+                            stored[(k, j, cs)] = stored.get((k, j, cs), 0) + 1
+                        c = f + 2 + cq
+                        first = T - 4 < T_start
+                        writes.append((("x", kk, jj, c % V7_W),
+                                       0 if first else old(j, k, c), wm))
+                        for a in ("r", "kx", "ky", "kz"):
+                            writes.append(((a, kk, jj, c % V7_W),
+                                           0 if first else arr(a, j, k, c),
+                                           wm))
+                        h16 = lane < 8
+                        hpl = not h16 and m == nw - 1 and lane < 40
+                        if not (h16 or hpl):
+                            continue
+                        hx = lane < 4 if h16 else ((lane - 8) >> 4) == 0
+                        hjj = 16 if h16 else 4 * p4 + (((lane - 8) >> 2) & 3)
+                        hkk = kk if h16 else KT
+                        hj, hk = j0 + hjj, k0 + hkk
+                        hc = T - (hj + hk) + 2 + cq
+                        a = "x" if hx else ("ky" if h16 else "kz")
+                        if first:
+                            v = 0
+                        elif hx:
+                            v = old(hj, hk, hc)
+                        else:
+                            v = arr(a, hj, hk, hc)
+                        writes.append(((a, hkk, hjj, hc % V7_W), v, wm))
+                wp = 2 * nw
+                for h in range(KT + 16):
+                    left = h < KT
+                    jj, kk = (-1, h) if left else (h - KT, -1)
+                    prod = (jt - 1, vt) if left else (jt, vt - 1)
+                    ent = h if left else (KT + jj if jj < 15 else KT - 1)
+                    j, k = j0 + jj, k0 + kk
+                    c = T - (j + k)
+                    if not (valid(j, k) and c >= 0):
+                        continue
+                    if c < nx:
+                        assert T - V7_POLL >= T_start
+                        assert ticket[prod] < ticket[(jt, vt)]
+                        jp, kp = j - V7_TJ * prod[0], k - KT * prod[1]
+                        pe = (kp if jp == 15 else
+                              (KT + jp if kp == KT - 1 else -1))
+                        assert pe == ent, (pe, ent)
+                        v = ("new", j, k, c)
+                    else:
+                        v = 0
+                    writes.append((("x", kk, jj, c % V7_W), v, wp))
+                for w in range(nw):
+                    for lane in range(64):
+                        jj, kk = lane & 15, 4 * w + (lane >> 4)
+                        j, k = j0 + jj, k0 + kk
+                        f = T - (j + k)
+                        if not (valid(j, k) and 0 <= f < nx):
+                            continue
+                        want = [
+                            (("x", kk, jj, (f + 1) % V7_W), old(j, k, f + 1)),
+                            (("x", kk, jj + 1, f % V7_W), old(j + 1, k, f)),
+                            (("x", kk + 1, jj, f % V7_W), old(j, k + 1, f)),
+                            (("x", kk, jj - 1, f % V7_W), new(j - 1, k, f)),
+                            (("x", kk - 1, jj, f % V7_W), new(j, k - 1, f)),
+                            (("r", kk, jj, f % V7_W), arr("r", j, k, f)),
+                            (("kx", kk, jj, f % V7_W), arr("kx", j, k, f)),
+                            (("kx", kk, jj, (f + 1) % V7_W),
+                             arr("kx", j, k, f + 1)),
+                            (("ky", kk, jj, f % V7_W), arr("ky", j, k, f)),
+                            (("ky", kk, jj + 1, f % V7_W),
+                             arr("ky", j + 1, k, f)),
+                            (("kz", kk, jj, f % V7_W), arr("kz", j, k, f)),
+                            (("kz", kk + 1, jj, f % V7_W),
+                             arr("kz", j, k + 1, f)),
+                        ]
+                        for slot, e_ in want:
+                            reads.append((slot, w, e_))
+                        writes.append((("x", kk, jj, f % V7_W),
+                                       ("new", j, k, f), w))
+                wsl = {}
+                for slot, v, w in writes:
+                    prev = wsl.get(slot)
+                    assert prev is None or prev[1] == w, ("write race", slot)
+                    wsl[slot] = (v, w)
+                for slot, w, e_ in reads:
+                    if slot in wsl:
+                        assert wsl[slot][1] == w, ("read/write race", slot, T)
+                    got = mem.get(slot, 0)
+                    assert got == e_, (T, slot, got, e_)
+                for slot, (v, w) in wsl.items():
+                    mem[slot] = v
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                assert stored.get((k, j, i)) == 1, ("store", (k, j, i))
+
+
+@pytest.mark.parametrize("shape", [(9, 7, 6), (5, 20, 11), (13, 17, 3),
+                                   (1, 1, 1), (4, 33, 5), (17, 16, 4)])
+@pytest.mark.parametrize("nw", [1, 2, 4])
+def test_v7_tile_model(shape, nw):
+    simulate_v7_tiles(shape, nw)
+
+
+def test_v7_tile_model_zero_start():
+    simulate_v7_tiles((6, 9, 5), 1, zero_start=True)
+
+
+@pytest.mark.parametrize("shape", [(9, 7, 6), (16, 16, 16), (13, 40, 9)])
+def test_v7_plan_matches_tile_model(shape, monkeypatch):
+    import torch
+    import paper_2204_13304_amd as m
+    nz, ny, nx = shape
+    for nw in (1, 2, 4):
+        monkeypatch.setenv("M2S_V7_WAVES", str(nw))
+        A = _fake_var7(m, shape)
+        p = m.plan_sweep(A)
+        assert p["slab_planes"] == 4 * nw
+        # nw compute + nw memory wavefronts + 1 poll wavefront
+        assert p["threads"] == 64 * (2 * nw + 1)
+        assert p["nslabs"] == -(-ny // V7_TJ) * -(-nz // (4 * nw))
