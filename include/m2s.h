@@ -136,11 +136,13 @@ m2s_status m2s_spmv_part(const m2s_stencil *A, int part, const void *x,
  *   descending (BWD), every neighbour taking its newest value.
  * CONST27 and VAR7, F64 and F32.  x is updated in place (via the
  * workspace's scratch vector); r is read-only; r and x must not overlap.
- * Executed as a persistent wavefront kernel: slabs of whole planes handed
- * to workgroups in dependency order, rows and planes inside a slab skewed
- * on the hyperplane i + 2j + 4k (CONST27) or i + j + k (VAR7), progress
- * flags between slabs.  The result is bitwise identical to the one-thread
- * lexicographic sweep m2s_symgs_sequential (same per-point arithmetic).
+ * Executed as a persistent wavefront kernel: point (i, j, k) runs at step
+ * i + 2j + 4k (CONST27) or i + j + k (VAR7) of the hyperplane schedule of
+ * Sec. 6.1.3; tiles of 16 rows by 4 planes per wavefront are handed to
+ * workgroups in dependency order and pass their boundary rows to their
+ * neighbours as epoch-tagged records.  The result is bitwise identical to
+ * the one-thread lexicographic sweep m2s_symgs_sequential (same per-point
+ * arithmetic).
  * --------------------------------------------------------------------- */
 m2s_status m2s_symgs(const m2s_stencil *A, const void *r, void *x,
                      m2s_dir dir, m2s_workspace *ws, hipStream_t stream);
@@ -174,13 +176,25 @@ m2s_status m2s_symgs_adjoint(const m2s_stencil *A, const void *g, void *gr,
  * NPB-LU shape, Sec. 7.1) for BLOCK7_5, F64:
  *   x_p <- (1 - omega) x_p + omega B0^{-1} (b_p - sum_{d} B_d x_{p+d}),
  * p ascending (FWD) / descending (BWD) / FWD then BWD (SYM = one SSOR
- * iteration).  B0^{-1} is applied through an LU factorisation with partial
- * pivoting computed once per call on the host.  x in place; b read-only.
- * Returns M2S_ERR_ARG if B0 is singular or omega is not in (0, 2).
+ * iteration).  Per call the host factors B0 (LU with partial pivoting) and
+ * forms omega B0^{-1} and omega B0^{-1} B_d, so a point is updated as
+ *   x_p <- g_p - sum_{lower d} omega B0^{-1} B_d x_{p+d},
+ *   g_p  = (1 - omega) x_p + omega B0^{-1} (b_p - sum_{upper d} B_d x_{p+d})
+ * (lower / upper in sweep order), the same value up to rounding.  Executed
+ * as a persistent wavefront kernel on the hyperplane i + j + k; x in place;
+ * b read-only; b and x must not overlap.  Returns M2S_ERR_ARG if B0 is
+ * singular or omega is not in (0, 2).
  * --------------------------------------------------------------------- */
 m2s_status m2s_ssor_sweep(const m2s_stencil *A, const void *b, void *x,
                           double omega, m2s_dir dir, m2s_workspace *ws,
                           hipStream_t stream);
+
+/* Reference: the same block SSOR sweep run by ONE GPU thread in plain
+ * lexicographic order, in place, with the same per-point arithmetic.  For
+ * testing the wavefront schedule only (slow); errors as m2s_ssor_sweep. */
+m2s_status m2s_ssor_sweep_sequential(const m2s_stencil *A, const void *b,
+                                     void *x, double omega, m2s_dir dir,
+                                     hipStream_t stream);
 
 /* ---------------------------------------------------------------------
  * Multigrid V-cycle (the HPCG MG of Sec. 7.1): levels obtained by halving

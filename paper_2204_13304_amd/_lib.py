@@ -73,6 +73,8 @@ _SIGS = {
     "m2s_symgs_sequential": (C.c_int, [_S, _P, _P, C.c_int, _P]),
     "m2s_symgs_adjoint": (C.c_int, [_S, _P, _P, _P, C.c_int, _P, _P]),
     "m2s_ssor_sweep": (C.c_int, [_S, _P, _P, C.c_double, C.c_int, _P, _P]),
+    "m2s_ssor_sweep_sequential": (C.c_int, [_S, _P, _P, C.c_double, C.c_int,
+                                            _P]),
     "m2s_mg_create": (C.c_int, [_S, C.c_int, C.c_int,
                                 C.POINTER(C.c_void_p)]),
     "m2s_mg_vcycle": (C.c_int, [_P, _P, _P, _P]),

@@ -219,6 +219,19 @@ def ssor_sweep(A: Stencil, b, x, omega, direction="sym",
     return x
 
 
+def ssor_sweep_sequential(A: Stencil, b, x, omega, direction="sym"):
+    """The block SSOR sweep by one GPU thread in lexicographic order (the
+    reference the wavefront kernel must match bitwise; slow)."""
+    lib = L.load()
+    _need(b, A.dtype, A.field_shape, "b")
+    _need(x, A.dtype, A.field_shape, "x")
+    L.check(lib.m2s_ssor_sweep_sequential(A.ref(), _ptr(b), _ptr(x),
+                                          float(omega), _DIRS[direction],
+                                          _stream()),
+            "m2s_ssor_sweep_sequential")
+    return x
+
+
 class MG:
     """Multigrid hierarchy; prec torch.float64 or torch.float32."""
 

@@ -50,6 +50,39 @@ hipError_t fill_block7_consts(const double *blocks, Block7Consts &C)
     for (int c = 0; c < 5; ++c) C.inv_udiag[c] = 1.0 / a[5 * c + c];
     return hipSuccess;
 }
+
+// The relaxation-factor products of a block SSOR sweep: D^{-1} column by
+// column from the LU factors (rows swapped as in the factorisation, then
+// forward and back substitution), G = w D^{-1}, W_d = w D^{-1} B_d.
+void set_block7_omega(Block7Consts &C, double omega)
+{
+    double Dinv[25];
+    for (int col = 0; col < 5; ++col) {
+        double y[5] = {0, 0, 0, 0, 0};
+        y[col] = 1.0;
+        for (int c = 0; c < 5; ++c)
+            if (C.piv[c] != c) std::swap(y[c], y[C.piv[c]]);
+        for (int r = 1; r < 5; ++r)
+            for (int c = 0; c < r; ++c) y[r] -= C.lu[5 * r + c] * y[c];
+        for (int r = 4; r >= 0; --r) {
+            for (int c = r + 1; c < 5; ++c) y[r] -= C.lu[5 * r + c] * y[c];
+            y[r] *= C.inv_udiag[r];
+        }
+        for (int r = 0; r < 5; ++r) Dinv[5 * r + col] = y[r];
+    }
+    for (int e = 0; e < 25; ++e) C.G[e] = omega * Dinv[e];
+    for (int e = 0; e < 25; ++e) C.W[0][e] = 0.0;
+    for (int d = 1; d < 7; ++d)
+        for (int r = 0; r < 5; ++r)
+            for (int c = 0; c < 5; ++c) {
+                double t = 0.0;
+                for (int q = 0; q < 5; ++q)
+                    t += Dinv[5 * r + q] * C.B[d][5 * q + c];
+                C.W[d][5 * r + c] = omega * t;
+            }
+    C.omb = 1.0 - omega;
+    C.omega = omega;
+}
 }  // namespace m2s
 
 struct m2s_workspace : public Workspace {};
@@ -192,12 +225,10 @@ m2s_status make_plan(const m2s_stencil &A, SweepPlan &P, bool with_grid)
         // rectangular tiles of 16 j by 4 * nw k, one lane per row
         if ((int64_t)nx * ny * nz * 40 >= ((int64_t)1 << 31))
             return M2S_ERR_SHAPE;
-        // one compute wavefront (4 planes) per tile: with its two memory
-        // wavefronts and the poll wavefront that is one per SIMD, which
-        // keeps the block arithmetic and the 4-step load pipelines in
-        // registers
-        int nw = env_int("M2S_B7_WAVES", 1);
-        if (nw != 1 && nw != 2) nw = 1;
+        // tiles of 16 j by 4 k: six wavefronts (compute, the two helpers
+        // that run ahead of it, two memory wavefronts, poll), each of the
+        // arithmetic ones holding its 75 block coefficients in registers
+        const int nw = 1;
         const B7Layout L = b7_layout(Grid{nx, ny, nz}, nw);
         if (L.bnd_elems * 16 >= ((int64_t)1 << 31)) return M2S_ERR_SHAPE;
         P.row_slots = 16;
@@ -560,6 +591,7 @@ m2s_status m2s_ssor_sweep(const m2s_stencil *A, const void *b, void *x,
     if (overlap(b, x, vb)) return M2S_ERR_ALIAS;
     Block7Consts C{};
     if (fill_block7_consts(A->blocks, C) != hipSuccess) return M2S_ERR_ARG;
+    set_block7_omega(C, omega);
     if (dir == M2S_SYM) {
         if ((st = half_sweep(*A, &C, omega, b, x, ws->scratch, false, false,
                              ws, stream)) != M2S_OK)
@@ -571,6 +603,28 @@ m2s_status m2s_ssor_sweep(const m2s_stencil *A, const void *b, void *x,
                          false, ws, stream)) != M2S_OK)
         return st;
     return hip_status(launch_copy(x, ws->scratch, (int64_t)vb, stream));
+}
+
+m2s_status m2s_ssor_sweep_sequential(const m2s_stencil *A, const void *b,
+                                     void *x, double omega, m2s_dir dir,
+                                     hipStream_t stream)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (A->kind != M2S_BLOCK7_5) return M2S_ERR_UNSUPPORTED;
+    if (!b || !x) return M2S_ERR_ARG;
+    if (!(omega > 0.0 && omega < 2.0)) return M2S_ERR_ARG;
+    if (dir != M2S_FWD && dir != M2S_BWD && dir != M2S_SYM) return M2S_ERR_ARG;
+    const size_t vb = (size_t)npoints(*A) * elem_size(*A);
+    if (overlap(b, x, vb)) return M2S_ERR_ALIAS;
+    Block7Consts C{};
+    if (fill_block7_consts(A->blocks, C) != hipSuccess) return M2S_ERR_ARG;
+    set_block7_omega(C, omega);
+    if (dir & M2S_FWD)
+        M2S_TRY(launch_sweep_sequential_b7(*A, C, omega, b, x, false, stream));
+    if (dir & M2S_BWD)
+        M2S_TRY(launch_sweep_sequential_b7(*A, C, omega, b, x, true, stream));
+    return M2S_OK;
 }
 
 m2s_status m2s_face_grad(const m2s_stencil *A, const double *u,

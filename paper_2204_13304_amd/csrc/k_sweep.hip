@@ -98,11 +98,12 @@ __device__ __forceinline__ T v7_point(const Virt<BWD> &V, const Faces &F,
                          kxm, kxp, kym, kyp, kzm, kzp);
 }
 
-// BLOCK7: x_p <- (1-w) x_p + w B0^{-1} (b_p - sum_{d=1..6} B_d x_{p+d}).
-// B0^{-1} through the LU factors with partial pivoting.
+// BLOCK7: x_p <- (1-w) x_p + w D^{-1} (b_p - sum_{d=1..6} B_d x_{p+d}),
+// through b7_upper / b7_relax / b7_lower (the relaxation factor is built
+// into the constants).
 template <bool BWD>
 __device__ __forceinline__ void b7_point(const Virt<BWD> &V,
-                                         const Block7Consts &C, double w,
+                                         const Block7Consts &C,
                                          const double *b, const double *xn,
                                          const double *xo, double *out,
                                          int iv, int jv, int kv)
@@ -110,27 +111,37 @@ __device__ __forceinline__ void b7_point(const Virt<BWD> &V,
     // sweep coordinates: (iv, jv, kv) - 1 are updated, + 1 are not
     const Grid &g = V.g;
     const int64_t p = V.idx(iv, jv, kv);
-    const int di[6] = {1, 0, 0, -1, 0, 0};
-    const int dj[6] = {0, 1, 0, 0, -1, 0};
-    const int dk[6] = {0, 0, 1, 0, 0, -1};
-    double xq[6][5], bb[5], old[5], res[5];
-    bool has[6];
+    const int di[3] = {1, 0, 0};
+    const int dj[3] = {0, 1, 0};
+    const int dk[3] = {0, 0, 1};
+    double xu[3][5], xl[3][5], bb[5], old[5], u[5], gg[5], res[5];
+    double Bu[3][25], Wl[3][25];
 #pragma unroll
-    for (int v = 0; v < 6; ++v) {
-        const int ii = iv + di[v], jj = jv + dj[v], kk = kv + dk[v];
-        has[v] = g.in(ii, jj, kk);
-        const double *src = v < 3 ? xo : xn;
-        const int64_t q = has[v] ? 5 * V.idx(ii, jj, kk) : 0;
+    for (int v = 0; v < 3; ++v) {
+        const int iu = iv + di[v], ju = jv + dj[v], ku = kv + dk[v];
+        const int il = iv - di[v], jl = jv - dj[v], kl = kv - dk[v];
+        const bool hu = g.in(iu, ju, ku), hl = g.in(il, jl, kl);
+        const int64_t qu = hu ? 5 * V.idx(iu, ju, ku) : 0;
+        const int64_t ql = hl ? 5 * V.idx(il, jl, kl) : 0;
 #pragma unroll
-        for (int c = 0; c < 5; ++c)
-            xq[v][c] = (has[v] && src) ? src[q + c] : 0.0;
+        for (int c = 0; c < 5; ++c) {
+            xu[v][c] = (hu && xo) ? xo[qu + c] : 0.0;
+            xl[v][c] = hl ? xn[ql + c] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < 25; ++e) {
+            Bu[v][e] = C.B[b7_upper_dir<BWD>(v)][e];
+            Wl[v][e] = C.W[b7_lower_dir<BWD>(v)][e];
+        }
     }
 #pragma unroll
     for (int a = 0; a < 5; ++a) {
         bb[a] = b[5 * p + a];
         old[a] = xo ? xo[5 * p + a] : 0.0;
     }
-    b7_combine<BWD>(C, w, bb, xq, has, old, res);
+    b7_upper(Bu, bb, xu, u);
+    b7_relax(C.G, C.omb, u, old, gg);
+    b7_lower(Wl, gg, xl, res);
 #pragma unroll
     for (int a = 0; a < 5; ++a) out[5 * p + a] = res[a];
 }
@@ -167,7 +178,7 @@ __device__ __forceinline__ void do_point(const SweepArgs<T> &a,
         a.xout[a.g.idx(i, j, k)] = v7_point<T, BWD>(
             V, F, a.kx, a.ky, a.kz, a.r, a.xout, a.xin, iv, jv, kv);
     } else {
-        b7_point<BWD>(V, b7, w, (const double *)a.r, (const double *)a.xout,
+        b7_point<BWD>(V, b7, (const double *)a.r, (const double *)a.xout,
                       (const double *)a.xin, (double *)a.xout, iv, jv, kv);
     }
 }

@@ -3,88 +3,85 @@
 // Sec. 7.1) as a persistent, tiled wavefront kernel for gfx950.
 //
 // Schedule.  Point (i, j, k) runs at step T = i + j + k, the hyperplane of
-// Eq. (hyperplane) with unit weights (Sec. 6.1.3): the three lower neighbours
-// have smaller T.  A tile is 16 consecutive j by KT = 4 * NW consecutive k,
-// one lane per row; the lower neighbours of its rows lie in the tile or in
-// tiles (j - 1, k) and (j, k - 1) of the tile grid (rectangular tiles are
-// acyclic for 7 points).  Tiles are handed out in lexicographic (k-tile,
-// j-tile) order from a ticket counter.
+// Eq. (hyperplane) with unit weights (Sec. 6.1.3): the three lower
+// neighbours have smaller T.  A tile is 16 consecutive j by 4 consecutive
+// k, one lane per row; the lower neighbours of its rows lie in the tile or
+// in tiles (j - 1, k) and (j, k - 1) of the tile grid (rectangular tiles
+// are acyclic for 7 points).  Tiles are handed out in lexicographic
+// (k-tile, j-tile) order from a ticket counter.
 //
-// Wavefront roles (as in the 27-point kernel): NW compute wavefronts (one
-// lane per row, LDS and FP64 only, plus the boundary publication), 2 NW
-// memory wavefronts (per compute wavefront one for x -- coalesced 4-column
-// windows of x_old in, finished pieces of x out -- and one for b and the
-// old-value halo rows; loads are parked 4 steps in registers), one poll
-// wavefront (the neighbour tiles' boundary records).  A value written by one
-// wavefront in step T is read by another from step T + 1 on.
-//  * LDS rings of 8 columns x 5 components per row.  At its front f a row
-//    reads its neighbours at column f and its own old value at f and f + 1;
-//    x_old is staged in windows [f + 2, f + 6), b in [f + 1, f + 5), and
-//    [f - 4, f) is stored, all by the row's memory wavefront at the row's
-//    phase of the 4-step cycle (the store read comes before the staging
-//    write that reuses its slots).
-//  * The arithmetic is b7_combine, shared with the sequential kernel.
-//  * Boundary rows (j0 + 15 of every plane, j0 .. j0 + 14 of the top plane)
-//    are published per step into a step-major slice of epoch-tagged records,
-//    one record per component; consumers poll them 4 steps ahead.
+// The point update is split into b7_upper / b7_relax / b7_lower, so that
+// only its last part -- the three lower neighbours' new values times
+// w D^{-1} B_d -- lies on the step-to-step critical path; the parts that
+// need only old values run ahead of the front in wavefronts of their own.
+// Each wavefront keeps the coefficients of its part in registers.  Roles
+// (b7_role maps them to wavefronts):
+//   0 compute   x(f) = g(f) - sum_lower W_d x_d at the row's front f
+//   1 upper     u(f + 2) = b - sum_upper B_d x_d (old values: the upper
+//               neighbours reach column f + 2 only after this step)
+//   2 relax     g(f + 1) = (1 - w) x_old(f + 1) + G u(f + 1)
+//   3 x memory  stages x_old windows [f + 4, f + 8), stores [f - 4, f)
+//               (loads are parked in registers for 8 steps, two services
+//               of the plane, to cover the memory latency)
+//   4 poll      the neighbour tiles' boundary records (new values)
+//   5 b memory  stages b windows [f + 3, f + 7) and the old values of the
+//               halo rows (row 16 of every plane, plane 4)
+// The memory wavefronts serve the 4 planes in turn, one per step, with
+// 4-column windows (element l + 64q -> row (l + 64q) / 20, column
+// ((l + 64q) % 20) / 5, component (l + 64q) % 5).  Every role runs the same
+// barriers; a value written by one wavefront in step T is read by another
+// from step T + 1 on.  Boundary rows (j0 + 15 of every plane, j0 .. j0 + 14
+// of the top plane) publish one epoch-tagged record per component and
+// step; consumers poll them 2 steps ahead.
 #include "m2s_internal.hpp"
+#include "tile_common.hpp"
 
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
-#include <vector>
 
 namespace m2s {
 
 constexpr int B7_TJ = 16;    // j-rows per tile
-constexpr int B7_RJ = 18;    // ring rows per plane: jj = -1 .. 16
-constexpr int B7_W = 8;      // ring columns
-constexpr int B7_RS = 41;    // ring row stride (doubles): 8 x 5 + 1
-constexpr int B7_POLL = 4;   // boundary poll distance (steps)
-constexpr int B7_PRE = 16;   // steps before the smallest row skew
+constexpr int B7_KT = 4;     // planes per tile
+constexpr int B7_RJ = 18;    // x-ring rows per plane: jj = -1 .. 16
+constexpr int B7_W = 16;     // x-ring columns
+constexpr int B7_RS = 81;    // x-ring row stride (doubles): 16 x 5 + 1
+constexpr int B7_BS = 41;    // b ring: 8 columns x 5 + 1
+constexpr int B7_US = 21;    // u and g rings: 4 columns x 5 + 1
+constexpr int B7_POLL = 2;   // boundary poll distance (steps): covers a
+                             // record round trip at this step time
+constexpr int B7_PRE = 20;   // steps before the smallest row skew
+constexpr int B7_NT = 384;   // six wavefronts
+// Role of wavefront w.  The arithmetic roles issue the most instructions
+// per step; wavefronts w and w + 4 share a SIMD, so compute and upper get a
+// SIMD each and the lighter roles go in pairs (b memory + poll, x memory +
+// relax).
+enum { R_COMPUTE, R_UPPER, R_RELAX, R_XMEM, R_POLL, R_BMEM };
+__device__ constexpr int b7_role(int w)
+{
+    return w == 0 ? R_BMEM
+         : w == 1 ? R_XMEM
+         : w == 2 ? R_COMPUTE
+         : w == 3 ? R_UPPER
+         : w == 4 ? R_POLL
+                  : R_RELAX;
+}
 
 namespace {
 
-// epoch-tagged FP64 record {lo, epoch, hi, epoch}, as in k_sweep27.hip
-using Rec4 = __attribute__((ext_vector_type(4))) unsigned;
-
-__device__ __forceinline__ Rec4 rec_make(double v, unsigned ep)
-{
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    return Rec4{(unsigned)b, ep, (unsigned)(b >> 32), ep};
-}
-__device__ __forceinline__ bool rec_ready(Rec4 r, unsigned ep)
-{
-    return r.y == ep && r.w == ep;
-}
-__device__ __forceinline__ double rec_value(Rec4 r)
-{
-    return __builtin_bit_cast(
-        double, (unsigned long long)r.x | ((unsigned long long)r.z << 32));
-}
-__device__ __forceinline__ Rec4 rec_load(__amdgpu_buffer_rsrc_t rs,
-                                         unsigned off)
-{
-    return __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 16);
-}
-__device__ __forceinline__ void rec_store(__amdgpu_buffer_rsrc_t rs,
-                                          unsigned off, Rec4 r)
-{
-    __builtin_amdgcn_raw_buffer_store_b128(r, rs, (int)off, 0, 16);
-}
 __device__ __forceinline__ double ld64(__amdgpu_buffer_rsrc_t rs,
                                        unsigned off)
 {
-    return __builtin_bit_cast(
-        double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
+    return buf_load<double>(rs, off);
 }
 __device__ __forceinline__ void st64(__amdgpu_buffer_rsrc_t rs, unsigned off,
                                      double v)
 {
-    __builtin_amdgcn_raw_buffer_store_b64(
-        __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v),
-        rs, (int)off, 0, 0);
+    buf_store<double, 0>(rs, off, v);
 }
+// keep a value in a vector register for the rest of the kernel
+__device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
 
 }  // namespace
 
@@ -94,7 +91,6 @@ struct B7Args {
     const double *b;
     const double *xin;     // nullptr: start from zero
     double *xout;
-    double w;
     void *bnd;             // boundary store (records)
     int64_t bnd_elems;     // records
     unsigned epoch;
@@ -104,251 +100,342 @@ struct B7Args {
     int spin_limit;
 };
 
-// C: device copy of the block constants.  As a separate read-only,
-// non-aliased argument its uniform reads compile to scalar loads.
-template <bool BWD, int NW>
-__global__ void __launch_bounds__(64 * (3 * NW + 1))
+// C: device copy of the block constants (read once per launch).
+template <bool BWD>
+__global__ void __launch_bounds__(B7_NT)
     b7_tile_kernel(B7Args a, const Block7Consts *__restrict__ C)
 {
-    constexpr int KT = 4 * NW;
+    using R = Rec<double>;
+    constexpr int KT = B7_KT;
     constexpr int NE = KT + 15;          // boundary rows per slice
     constexpr int WB = 5 * NE;           // records per slice
     constexpr int NH = 5 * (KT + 16);    // polled halo records
-    constexpr int NRING = (KT + 2) * B7_RJ;
-    constexpr int PS = B7_RJ * B7_RS;    // ring plane stride
-    constexpr int NT = 64 * (3 * NW + 1);
-    constexpr unsigned RB = 16;
+    constexpr int NXR = (KT + 2) * B7_RJ;
+    constexpr int PS = B7_RJ * B7_RS;    // x-ring plane stride
+    constexpr unsigned RB = R::bytes;
     extern __shared__ unsigned char smem_raw[];
     double *const xr = (double *)smem_raw;
-    double *const rr = xr + NRING * B7_RS;
+    double *const br = xr + NXR * B7_RS;
+    double *const ur = br + KT * B7_TJ * B7_BS;
+    double *const gr = ur + KT * B7_TJ * B7_US;
     __shared__ int s_tile, s_abort;
 
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const int last = (int)a.g.size() - 1;
-    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
+    const int tid = threadIdx.x, l = tid & 63;
+    const int role = b7_role(tid >> 6);
     const int dir = BWD ? -1 : 1;
     const unsigned OOB = 0x80000000u;
     const int nbytes = (int)((unsigned)(last + 1) * 40u);
     const unsigned ep = a.epoch;
 
-    auto xrow = [&](int kq, int jq) -> double * {
-        return xr + ((kq + 1) * B7_RJ + (jq + 1)) * B7_RS;
+    // x-ring index of (plane kq, row jq), column 0, component 0
+    auto xi = [](int kq, int jq) -> int {
+        return ((kq + 1) * B7_RJ + (jq + 1)) * B7_RS;
     };
-    auto rrow = [&](int kq, int jq) -> double * {
-        return rr + (kq * B7_TJ + jq) * B7_RS;
-    };
-    // element (double) index of virtual column 0, component 0 of row (j, k)
+    // element index of sweep-order column 0, component 0 of row (j, k)
     auto rowbase = [&](int j, int k) -> int {
         const int v = (k * ny + j) * nx;
         return 5 * (BWD ? last - v : v);
     };
-    // byte offset of (column c, component q) of a row; OOB outside
-    auto boff = [&](bool vrow, int rb, int c, int q) -> unsigned {
-        return (vrow && (unsigned)c < (unsigned)nx)
-                   ? (unsigned)(rb + dir * 5 * c + q) * 8u
-                   : OOB;
-    };
 
     if (tid == 0) s_abort = 0;
-    bool aborted = false;
-    for (;;) {
+    int jt = 0, vt = 0, j0 = 0, k0 = 0, T0 = 0, T_start = 0, nblk = 0;
+    // Every role runs this tile loop with the same barriers.
+    auto next_tile = [&]() -> bool {
         __syncthreads();
         if (tid == 0) {
             uint64_t tk = atomicAdd((unsigned long long *)a.ticket, 1ull) -
                           a.ticket_base;
-            s_tile = tk < (uint64_t)a.ntiles ? (int)tk : -1;
+            s_tile = (tk < (uint64_t)a.ntiles && !s_abort) ? (int)tk : -1;
         }
-        for (int e = tid; e < NRING * B7_RS; e += NT) xr[e] = 0.0;
+        for (int e = tid; e < NXR * B7_RS; e += B7_NT) xr[e] = 0.0;
         __syncthreads();
         const int tile = s_tile;
-        if (tile < 0 || aborted) return;
-        const int jt = tile % a.njt, vt = tile / a.njt;
-        const int j0 = B7_TJ * jt, k0 = KT * vt;
-        const int T0 = j0 + k0;
-        const int T_start = T0 - 1 - B7_PRE;
+        if (tile < 0) return false;
+        jt = tile % a.njt;
+        vt = tile / a.njt;
+        j0 = B7_TJ * jt;
+        k0 = KT * vt;
+        T0 = j0 + k0;
+        T_start = T0 - 1 - B7_PRE;
         const int T_lastc = T0 + (B7_TJ - 1) + (KT - 1) + nx - 1;
-        const int nblk = (T_lastc + 5 - T_start + 15) / 16;
+        nblk = (T_lastc + 5 - T_start + 15) / 16;
+        return true;
+    };
+    const __amdgpu_buffer_rsrc_t rs_b = __builtin_amdgcn_make_buffer_rsrc(
+        a.bnd, 0, (int)(a.bnd_elems * RB), 0x00020000);
 
-        if (wv < NW) {
-            // ================= compute: row (j0 + jj, k0 + kk) =============
-            const int jj = l & 15, kk = 4 * wv + (l >> 4);
+    if (role <= R_RELAX) {
+        // ====== compute / upper / relax: lane = row (j0 + jj, k0 + kk) =====
+        const int jj = l & 15, kk = l >> 4;
+        double cf[3][25];
+        double omb = 0.0;
+#pragma unroll
+        for (int v = 0; v < 3; ++v)
+#pragma unroll
+            for (int e = 0; e < 25; ++e) {
+                cf[v][e] = role == R_COMPUTE ? C->W[b7_lower_dir<BWD>(v)][e]
+                           : role == R_UPPER ? C->B[b7_upper_dir<BWD>(v)][e]
+                                             : (v == 0 ? C->G[e] : 0.0);
+                pin(cf[v][e]);
+            }
+        if (role == R_RELAX) omb = C->omb;
+        double *const own = xr + xi(kk, jj);
+        double *const bown = br + (kk * B7_TJ + jj) * B7_BS;
+        double *const uown = ur + (kk * B7_TJ + jj) * B7_US;
+        double *const gown = gr + (kk * B7_TJ + jj) * B7_US;
+        while (next_tile()) {
             const int j = j0 + jj, k = k0 + kk;
             const bool vc = j < ny && k < nz;
             const int sc = j + k;
-            double *const own = xrow(kk, jj);
-            double *const rown = rrow(kk, jj);
-            const int ipub =
-                jj == 15 ? kk : (kk == KT - 1 ? KT + jj : -1);
-            const bool pub = vc && ipub >= 0;
-            const int bout = (vt * a.njt + jt) * a.ns * WB + 5 * ipub - T0 * WB;
-            const bool hym = j > 0, hyp = j + 1 < ny, hzm = k > 0,
-                       hzp = k + 1 < nz;
-            const __amdgpu_buffer_rsrc_t rs_b =
-                __builtin_amdgcn_make_buffer_rsrc(
-                    a.bnd, 0, (int)(a.bnd_elems * RB), 0x00020000);
-            double xprev[5];
-#pragma unroll
-            for (int c = 0; c < 5; ++c) xprev[c] = 0.0;
-            for (int blk = 0; blk < nblk; ++blk) {
-                const int Tb = T_start + 16 * blk;
-#pragma unroll 1
-                for (int ph = 0; ph < 16; ++ph) {
-                    const int st = Tb + ph;
-                    const int f = st - sc;
-                    const int o0 = (f & (B7_W - 1)) * 5;
-                    // the block coefficients are read through the scalar
-                    // cache every step (an opaque zero offset keeps the
-                    // reads in the loop instead of in registers across it)
-                    int zc = 0;
-                    asm volatile("" : "+s"(zc));
-                    const Block7Consts &Cs =
-                        *(const Block7Consts *)((const char *)C + zc);
-                    const int o1 = ((f + 1) & (B7_W - 1)) * 5;
-                    double xq[6][5], bb[5], old[5], res[5];
-#pragma unroll
-                    for (int c = 0; c < 5; ++c) {
-                        xq[0][c] = own[o1 + c];            // +x, old
-                        xq[1][c] = own[o0 + B7_RS + c];    // +y, old
-                        xq[2][c] = own[o0 + PS + c];       // +z, old
-                        xq[3][c] = xprev[c];               // -x, new
-                        xq[4][c] = own[o0 - B7_RS + c];    // -y, new
-                        xq[5][c] = own[o0 - PS + c];       // -z, new
-                        old[c] = own[o0 + c];
-                        bb[c] = rown[o0 + c];
-                    }
-                    const bool has[6] = {f + 1 < nx, hyp, hzp, f > 0, hym,
-                                         hzm};
-                    b7_combine<BWD>(Cs, a.w, bb, xq, has, old, res);
-                    const bool act = vc && (unsigned)f < (unsigned)nx;
-                    if (act) {
+            if (role == R_COMPUTE) {
+                const int ipub =
+                    jj == 15 ? kk : (kk == KT - 1 ? KT + jj : -1);
+                const bool pub = vc && ipub >= 0;
+                const int bout =
+                    (vt * a.njt + jt) * a.ns * WB + 5 * ipub - T0 * WB;
+                double xp[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+                for (int blk = 0; blk < nblk; ++blk) {
+                    const int Tb = T_start + 16 * blk;
+#pragma unroll 2
+                    for (int ph = 0; ph < 16; ++ph) {
+                        const int st = Tb + ph;
+                        const int f = st - sc;
+                        const int o = (f & (B7_W - 1)) * 5;
+                        const int og = (f & 3) * 5;
+                        double g[5], xn[3][5], x[5];
 #pragma unroll
                         for (int c = 0; c < 5; ++c) {
-                            own[o0 + c] = res[c];
-                            xprev[c] = res[c];
+                            g[c] = gown[og + c];
+                            xn[0][c] = xp[c];                 // -x
+                            xn[1][c] = own[o - B7_RS + c];    // -y
+                            xn[2][c] = own[o - PS + c];       // -z
                         }
-                    }
-                    const int rec = bout + st * WB;
+                        b7_lower(cf, g, xn, x);
+                        const bool act = vc && (unsigned)f < (unsigned)nx;
+                        if (act) {
 #pragma unroll
-                    for (int c = 0; c < 5; ++c)
-                        rec_store(rs_b,
-                                  act && pub ? (unsigned)(rec + c) * RB : OOB,
-                                  rec_make(res[c], ep));
-                    __syncthreads();
+                            for (int c = 0; c < 5; ++c) {
+                                own[o + c] = x[c];
+                                xp[c] = x[c];
+                            }
+                        }
+                        const int rec = bout + st * WB;
+#pragma unroll
+                        for (int c = 0; c < 5; ++c)
+                            R::store(rs_b,
+                                     act && pub ? (unsigned)(rec + c) * RB
+                                                : OOB,
+                                     R::make(x[c], ep));
+                        __syncthreads();
+                    }
+                    if (s_abort) break;
                 }
-                if (s_abort) {
-                    aborted = true;
-                    break;
+            } else if (role == R_UPPER) {
+                for (int blk = 0; blk < nblk; ++blk) {
+                    const int Tb = T_start + 16 * blk;
+#pragma unroll 2
+                    for (int ph = 0; ph < 16; ++ph) {
+                        const int st = Tb + ph;
+                        const int c = st - sc + 2;
+                        const int ox = (c & (B7_W - 1)) * 5;
+                        const int ox1 = ((c + 1) & (B7_W - 1)) * 5;
+                        const int ob = (c & 7) * 5, ou = (c & 3) * 5;
+                        double bv[5], xo[3][5], u[5];
+#pragma unroll
+                        for (int q = 0; q < 5; ++q) {
+                            bv[q] = bown[ob + q];
+                            xo[0][q] = own[ox1 + q];          // +x
+                            xo[1][q] = own[ox + B7_RS + q];   // +y
+                            xo[2][q] = own[ox + PS + q];      // +z
+                        }
+                        b7_upper(cf, bv, xo, u);
+#pragma unroll
+                        for (int q = 0; q < 5; ++q) uown[ou + q] = u[q];
+                        __syncthreads();
+                    }
+                    if (s_abort) break;
+                }
+            } else {
+                for (int blk = 0; blk < nblk; ++blk) {
+                    const int Tb = T_start + 16 * blk;
+#pragma unroll 2
+                    for (int ph = 0; ph < 16; ++ph) {
+                        const int st = Tb + ph;
+                        const int c = st - sc + 1;
+                        const int ox = (c & (B7_W - 1)) * 5, ou = (c & 3) * 5;
+                        double uv[5], xo[5], g[5];
+#pragma unroll
+                        for (int q = 0; q < 5; ++q) {
+                            uv[q] = uown[ou + q];
+                            xo[q] = own[ox + q];
+                        }
+                        b7_relax(cf[0], omb, uv, xo, g);
+#pragma unroll
+                        for (int q = 0; q < 5; ++q) gown[ou + q] = g[q];
+                        __syncthreads();
+                    }
+                    if (s_abort) break;
                 }
             }
-        } else if (wv < 3 * NW) {
-            // ====== memory wavefronts of compute wavefront m: x (stage
-            //        x_old, store finished x) or b (stage b and the
-            //        old-value halo rows) ======
-            // At step T the 16 rows of plane 4m + (T mod 4) get 4-column
-            // windows: lane element e = l + 64q -> row e / 20, column
-            // (e % 20) / 5, component e % 5.
-            const bool xw_role = wv < 2 * NW;
-            const int m = xw_role ? wv - NW : wv - 2 * NW;
-            const __amdgpu_buffer_rsrc_t rs_in =
-                xw_role ? __builtin_amdgcn_make_buffer_rsrc(
-                              (void *)(a.xin ? a.xin : a.b), 0,
-                              a.xin ? nbytes : 0, 0x00020000)
-                        : __builtin_amdgcn_make_buffer_rsrc(
-                              (void *)a.b, 0, nbytes, 0x00020000);
-            const __amdgpu_buffer_rsrc_t rs_x =
-                __builtin_amdgcn_make_buffer_rsrc(
-                    (void *)(a.xin ? a.xin : a.b), 0, a.xin ? nbytes : 0,
-                    0x00020000);
-            const __amdgpu_buffer_rsrc_t rs_o =
-                __builtin_amdgcn_make_buffer_rsrc((void *)a.xout, 0, nbytes,
-                                                  0x00020000);
-            // window start relative to the front: x_old 2, b 1
-            const int lead = xw_role ? 2 : 1;
-            double pipe[4][5], hpipe[4][2];
+        }
+    } else if (role == R_XMEM || role == R_BMEM) {
+        // ====== memory wavefronts ======
+        // Per plane p (served at steps T with (T - T_start) mod 4 = p) and
+        // element q the step-independent parts of the addresses: column
+        // c = T + kc + lead, x- or b-ring index li + 5 (c mod ring), and
+        // element index gb + 5 dir c (columns run backwards in memory in a
+        // backward sweep, the 5 components of a point never do).  Rows
+        // outside the grid get kc far below 0, so every column test fails
+        // and their loads read 0; their ring slots hold 0.
+        const bool xw = role == R_XMEM;
+        const __amdgpu_buffer_rsrc_t rs_x = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(a.xin ? a.xin : a.b), 0, a.xin ? nbytes : 0, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rs_bb = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)a.b, 0, nbytes, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rs_o = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)a.xout, 0, nbytes, 0x00020000);
+        constexpr int NOFF = -(1 << 28);
+        double pipe[2][4][5], hpipe[2][4][2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
 #pragma unroll
-                for (int q = 0; q < 5; ++q) pipe[p][q] = 0.0;
-                hpipe[p][0] = hpipe[p][1] = 0.0;
+                for (int q = 0; q < 5; ++q) pipe[h][p][q] = 0.0;
+                hpipe[h][p][0] = hpipe[h][p][1] = 0.0;
+            }
+        const int plane_elems = 5 * ny * nx;  // elements per plane
+        while (next_tile()) {
+            // plane 0 of the tile; plane p adds p planes (uniform), and a
+            // plane of rows at or past nz has no points
+            int kc0[5], li0[5], gb0[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                const int e = l + 64 * q;
+                const int jj = e / 20, o = e % 20;
+                const int cq = o / 5, comp = o % 5;
+                const int j = j0 + jj;
+                kc0[q] = j < ny ? cq - (j + k0) : NOFF;
+                li0[q] = xw ? xi(0, jj) + comp : jj * B7_BS + comp;
+                gb0[q] = j < ny ? rowbase(j, k0) + comp : 0;
+            }
+            // halo elements (b wavefront): e < 20 row (16, p) of plane p;
+            // 20 <= e < 100 plane 4, row 4p + (e - 20) / 20.  Between the
+            // planes p the first kind moves one plane, the second 4 rows.
+            int hkc0[2], hli0[2], hgb0[2], hm[2], hls[2], hgs[2], hj[2];
+            bool hisa[2], hany[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int e = l + 64 * q;
+                const bool isa = e < 20, ispl = e >= 20 && e < 100;
+                const int r = isa ? 16 : (e - 20) / 20;
+                const int o = isa ? e : (e - 20) % 20;
+                const int hkk = isa ? 0 : KT;
+                const int cq = o / 5, comp = o % 5;
+                hisa[q] = isa;
+                hany[q] = isa || ispl;
+                hj[q] = j0 + r;
+                hm[q] = isa ? 1 : 4;
+                hls[q] = isa ? PS : 4 * B7_RS;
+                hgs[q] = isa ? dir * plane_elems : dir * 20 * nx;
+                hkc0[q] = cq - (j0 + r + k0 + hkk);
+                hli0[q] = hany[q] ? xi(hkk, r) + comp : 0;
+                hgb0[q] = rowbase(min(j0 + r, ny - 1), min(k0 + hkk, nz - 1)) +
+                          comp;
+                if (!isa && k0 + hkk >= nz) hgb0[q] = 0;
             }
             for (int blk = 0; blk < nblk; ++blk) {
                 const int Tb = T_start + 16 * blk;
 #pragma unroll 1
-                for (int ph0 = 0; ph0 < 16; ph0 += 4)
+                for (int ph0 = 0; ph0 < 16; ph0 += 8)
 #pragma unroll
-                for (int p4 = 0; p4 < 4; ++p4) {
-                    const int st = Tb + ph0 + p4;
-                    const int kk = 4 * m + p4;
-                    if (xw_role) {
-                        // all store reads first: a row's window spans two
-                        // element groups, and the staging writes below
-                        // reuse the slots of the stored columns
+                for (int s8 = 0; s8 < 8; ++s8) {
+                    // plane p, pipeline half h: a load issued now is
+                    // written to the ring 8 steps later
+                    const int p = s8 & 3, h = s8 >> 2;
+                    const int st = Tb + ph0 + s8;
+                    const bool pin_k = k0 + p < nz;
+                    if (xw) {
+                        // store [f - 4, f), then stage [f + 4, f + 8)
 #pragma unroll
                         for (int q = 0; q < 5; ++q) {
-                            const int e = l + 64 * q;
-                            const int jj = e / 20, o = e % 20;
-                            const int cq = o / 5, comp = o % 5;
-                            const int j = j0 + jj, k = k0 + kk;
-                            const bool v = j < ny && k < nz;
-                            const int cs = st - (j + k) - 4 + cq;
-                            const double xv =
-                                xrow(kk, jj)[(cs & (B7_W - 1)) * 5 + comp];
+                            const int kc = pin_k ? kc0[q] - p : NOFF;
+                            const int li = li0[q] + p * PS;
+                            const int gb = gb0[q] + p * dir * plane_elems;
+                            const int cs = st + kc - 4;
+                            const double xv = xr[li + (cs & (B7_W - 1)) * 5];
                             st64(rs_o,
-                                 boff(v, v ? rowbase(j, k) : 0, cs, comp), xv);
+                                 (unsigned)cs < (unsigned)nx
+                                     ? (unsigned)(gb + dir * 5 * cs) * 8u
+                                     : OOB,
+                                 xv);
                         }
-                    }
 #pragma unroll
-                    for (int q = 0; q < 5; ++q) {
-                        const int e = l + 64 * q;
-                        const int jj = e / 20, o = e % 20;
-                        const int cq = o / 5, comp = o % 5;
-                        const int j = j0 + jj, k = k0 + kk;
-                        const bool v = j < ny && k < nz;
-                        const int c = st - (j + k) + lead + cq;
-                        double *const dst =
-                            xw_role ? xrow(kk, jj) : rrow(kk, jj);
-                        dst[(c & (B7_W - 1)) * 5 + comp] = pipe[p4][q];
-                        pipe[p4][q] = ld64(
-                            rs_in, boff(v, v ? rowbase(j, k) : 0, c + 4, comp));
-                    }
-                    if (!xw_role) {
-                        // old-value halo rows: (16, 4m + p4) and, for the
-                        // last wavefront, plane KT rows 4 p4 .. 4 p4 + 3
+                        for (int q = 0; q < 5; ++q) {
+                            const int kc = pin_k ? kc0[q] - p : NOFF;
+                            const int li = li0[q] + p * PS;
+                            const int gb = gb0[q] + p * dir * plane_elems;
+                            const int cx = st + kc + 4;
+                            xr[li + (cx & (B7_W - 1)) * 5] = pipe[h][p][q];
+                            const int cl = cx + 8;
+                            pipe[h][p][q] = ld64(
+                                rs_x, (unsigned)cl < (unsigned)nx
+                                          ? (unsigned)(gb + dir * 5 * cl) * 8u
+                                          : OOB);
+                        }
+                    } else {
+                        // stage b [f + 3, f + 7)
+#pragma unroll
+                        for (int q = 0; q < 5; ++q) {
+                            const int kc = pin_k ? kc0[q] - p : NOFF;
+                            const int li = li0[q] + p * B7_TJ * B7_BS;
+                            const int gb = gb0[q] + p * dir * plane_elems;
+                            const int cb = st + kc + 3;
+                            br[li + (cb & 7) * 5] = pipe[h][p][q];
+                            const int cl = cb + 8;
+                            pipe[h][p][q] = ld64(
+                                rs_bb, (unsigned)cl < (unsigned)nx
+                                           ? (unsigned)(gb + dir * 5 * cl) * 8u
+                                           : OOB);
+                        }
+                        // old values of the halo rows, [f + 4, f + 8)
 #pragma unroll
                         for (int q = 0; q < 2; ++q) {
-                            const int e = l + 64 * q;
-                            const bool isa = e < 20;
-                            const bool mine =
-                                isa || (m == NW - 1 && e < 100);
-                            const int jj = isa ? 16 : 4 * p4 + (e - 20) / 20;
-                            const int o = isa ? e : (e - 20) % 20;
-                            const int kq = isa ? kk : KT;
-                            const int cq = o / 5, comp = o % 5;
-                            const int j = j0 + jj, k = k0 + kq;
-                            const bool v = mine && j < ny && k < nz;
-                            const int cx = st - (j + k) + 2 + cq;
-                            if (mine)
-                                xrow(kq, jj)[(cx & (B7_W - 1)) * 5 + comp] =
-                                    hpipe[p4][q];
-                            hpipe[p4][q] = ld64(
-                                rs_x,
-                                boff(v, v ? rowbase(j, k) : 0, cx + 4, comp));
+                            const bool hv =
+                                hany[q] &&
+                                (hisa[q] ? hj[q] < ny && pin_k
+                                         : hj[q] + 4 * p < ny && k0 + KT < nz);
+                            const int kc = hv ? hkc0[q] - hm[q] * p : NOFF;
+                            const int li = hli0[q] + p * hls[q];
+                            const int gb = hgb0[q] + p * hgs[q];
+                            const int ch = st + kc + 4;
+                            if (hany[q])
+                                xr[li + (ch & (B7_W - 1)) * 5] = hpipe[h][p][q];
+                            const int cl = ch + 8;
+                            hpipe[h][p][q] = ld64(
+                                rs_x, (unsigned)cl < (unsigned)nx
+                                          ? (unsigned)(gb + dir * 5 * cl) * 8u
+                                          : OOB);
                         }
                     }
                     __syncthreads();
                 }
-                if (s_abort) {
-                    aborted = true;
-                    break;
-                }
+                if (s_abort) break;
             }
-        } else {
-            // ====== poll wavefront: records l and l + 64 of the halo ======
-            // halo row h < KT: (jj = -1, kk = h) from tile (jt - 1, vt),
-            // entry h; h = KT + jj: plane k0 - 1 row jj from (jt, vt - 1),
-            // entry KT + jj (jj < 15) or KT - 1 (jj = 15)
-            int hoff[2], hs[2], hslot[2], hT0[2];
-            double *hrow[2];
+        }
+    } else {
+        // ====== poll wavefront: records l and l + 64 of the halo ======
+        // halo row h < KT: (jj = -1, kk = h) from tile (jt - 1, vt), entry h;
+        // h = KT + jj: plane k0 - 1 row jj from (jt, vt - 1), entry KT + jj
+        // (jj < 15) or KT - 1 (jj = 15)
+        typename R::V ppipe[B7_POLL][2];
+#pragma unroll
+        for (int p = 0; p < B7_POLL; ++p) ppipe[p][0] = ppipe[p][1] = R::V{};
+        int spin_budget = a.spin_limit;
+        while (next_tile()) {
+            int hs[2], hslot[2], hT0[2], hx[2];
             bool hv[2];
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
@@ -366,21 +453,12 @@ __global__ void __launch_bounds__(64 * (3 * NW + 1))
                 hslot[q] = hv[q] ? (pvt * a.njt + pjt) * a.ns * WB + 5 * ent +
                                        comp
                                  : 0;
-                hrow[q] = xrow(hv[q] ? kk : 0, hv[q] ? jj : 0) + comp;
-                hoff[q] = comp;
+                hx[q] = xi(hv[q] ? kk : 0, hv[q] ? jj : 0) + comp;
             }
-            (void)hoff;
-            const __amdgpu_buffer_rsrc_t rs_b =
-                __builtin_amdgcn_make_buffer_rsrc(
-                    a.bnd, 0, (int)(a.bnd_elems * RB), 0x00020000);
             auto pslice = [&](int q, int T_) -> int {
                 const int s = min(max(T_ - hT0[q], 0), a.ns - 1);
                 return hslot[q] + s * WB;
             };
-            Rec4 ppipe[B7_POLL][2];
-#pragma unroll
-            for (int p = 0; p < B7_POLL; ++p) ppipe[p][0] = ppipe[p][1] = Rec4{};
-            int spin_budget = a.spin_limit;
             for (int blk = 0; blk < nblk; ++blk) {
                 const int Tb = T_start + 16 * blk;
 #pragma unroll 1
@@ -394,10 +472,10 @@ __global__ void __launch_bounds__(64 * (3 * NW + 1))
                         if (hv[q] && c >= 0) {
                             double v = 0.0;
                             if (c < nx) {
-                                Rec4 r = ppipe[ph & (B7_POLL - 1)][q];
+                                typename R::V r = ppipe[ph & (B7_POLL - 1)][q];
                                 const unsigned src =
                                     (unsigned)pslice(q, st) * RB;
-                                while (!rec_ready(r, ep)) {
+                                while (!R::ready(r, ep)) {
                                     if (--spin_budget < 0 ||
                                         __hip_atomic_load(
                                             a.err, __ATOMIC_RELAXED,
@@ -410,22 +488,19 @@ __global__ void __launch_bounds__(64 * (3 * NW + 1))
                                         break;
                                     }
                                     __builtin_amdgcn_s_sleep(1);
-                                    r = rec_load(rs_b, src);
+                                    r = R::load(rs_b, src);
                                 }
-                                v = rec_value(r);
+                                v = R::value(r);
                             }
-                            hrow[q][(c & (B7_W - 1)) * 5] = v;
+                            xr[hx[q] + (c & (B7_W - 1)) * 5] = v;
                         }
-                        ppipe[ph & (B7_POLL - 1)][q] = rec_load(
+                        ppipe[ph & (B7_POLL - 1)][q] = R::load(
                             rs_b, hv[q] ? (unsigned)pslice(q, st + B7_POLL) * RB
                                         : OOB);
                     }
                     __syncthreads();
                 }
-                if (s_abort) {
-                    aborted = true;
-                    break;
-                }
+                if (s_abort) break;
             }
         }
     }
@@ -437,7 +512,7 @@ B7Layout b7_layout(Grid g, int nw)
 {
     B7Layout L{};
     L.nw = nw;
-    L.kt = 4 * nw;
+    L.kt = B7_KT;
     L.njt = (g.ny + B7_TJ - 1) / B7_TJ;
     L.nbands = (g.nz + L.kt - 1) / L.kt;
     L.ntiles = L.njt * L.nbands;
@@ -447,20 +522,20 @@ B7Layout b7_layout(Grid g, int nw)
     return L;
 }
 
-size_t b7_lds_bytes(int nw)
+size_t b7_lds_bytes(int)
 {
-    const int kt = 4 * nw;
-    return ((size_t)(kt + 2) * B7_RJ + (size_t)kt * B7_TJ) * B7_RS * 8;
+    return ((size_t)(B7_KT + 2) * B7_RJ * B7_RS +
+            (size_t)B7_KT * B7_TJ * (B7_BS + 2 * B7_US)) *
+           8;
 }
 
-int b7_threads(int nw) { return 64 * (3 * nw + 1); }
+int b7_threads(int) { return B7_NT; }
 
-template <bool BWD, int NW>
+template <bool BWD>
 static hipError_t b7_launch_t(const B7Args &a, const Block7Consts *C,
-                              int grid, size_t lds,
-                              hipStream_t s)
+                              int grid, size_t lds, hipStream_t s)
 {
-    auto k = b7_tile_kernel<BWD, NW>;
+    auto k = b7_tile_kernel<BWD>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(
@@ -469,7 +544,7 @@ static hipError_t b7_launch_t(const B7Args &a, const Block7Consts *C,
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * (3 * NW + 1)), lds, s, a, C);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(B7_NT), lds, s, a, C);
     return hipGetLastError();
 }
 
@@ -478,6 +553,7 @@ hipError_t launch_sweep7(const m2s_stencil &A, const Block7Consts &C,
                          void *xout, bool bwd, Workspace &ws,
                          const SweepPlan &plan, hipStream_t s)
 {
+    (void)omega;  // built into C (set_block7_omega)
     // device copy of the block constants, refreshed when they change
     if (!ws.b7c) {
         hipError_t e = hipMalloc(&ws.b7c, sizeof(Block7Consts));
@@ -494,8 +570,7 @@ hipError_t launch_sweep7(const m2s_stencil &A, const Block7Consts &C,
         std::memcpy(&ws.b7c_host, &C, sizeof(Block7Consts));
         ws.b7c_valid = true;
     }
-    const int nw = plan.slab_planes / 4;
-    const size_t lds = b7_lds_bytes(nw);
+    const size_t lds = b7_lds_bytes(1);
     const uint64_t base = ws.ticket_base;
     ws.ticket_base += (uint64_t)plan.nslabs + (uint64_t)plan.grid;
     if (++ws.epoch == 0) ++ws.epoch;
@@ -507,7 +582,6 @@ hipError_t launch_sweep7(const m2s_stencil &A, const Block7Consts &C,
     a.b = (const double *)b;
     a.xin = (const double *)xin;
     a.xout = (double *)xout;
-    a.w = omega;
     a.bnd = ws.bnd;
     a.bnd_elems = ws.bnd_elems;
     a.epoch = ws.epoch;
@@ -517,15 +591,8 @@ hipError_t launch_sweep7(const m2s_stencil &A, const Block7Consts &C,
     const char *e = getenv("M2S_SPIN_LIMIT");
     a.spin_limit = e ? std::max(1, atoi(e)) : (1 << 22);
     const Block7Consts *cd = (const Block7Consts *)ws.b7c;
-    switch (nw) {
-    case 1:
-        return bwd ? b7_launch_t<true, 1>(a, cd, plan.grid, lds, s)
-                   : b7_launch_t<false, 1>(a, cd, plan.grid, lds, s);
-    case 2:
-        return bwd ? b7_launch_t<true, 2>(a, cd, plan.grid, lds, s)
-                   : b7_launch_t<false, 2>(a, cd, plan.grid, lds, s);
-    }
-    return hipErrorInvalidValue;
+    return bwd ? b7_launch_t<true>(a, cd, plan.grid, lds, s)
+               : b7_launch_t<false>(a, cd, plan.grid, lds, s);
 }
 
 }  // namespace m2s

@@ -60,14 +60,20 @@ struct Faces {
     __host__ __device__ int64_t nfz() const { return (int64_t)(nz + 1) * ny * nx; }
 };
 
-// BLOCK7 constants passed by value: the seven 5x5 blocks, and the LU
-// factorisation with partial pivoting of the centre block (unit lower L
-// below the diagonal, U on and above; inverse pivots precomputed).
+// BLOCK7 constants: the seven 5x5 blocks B_d (order C, -x, +x, -y, +y, -z,
+// +z; row-major), the LU factorisation with partial pivoting of the centre
+// block D = B_0 (unit lower L below the diagonal, U on and above; inverse
+// pivots precomputed), and for the relaxation factor w of a block SSOR
+// sweep W_d = w D^{-1} B_d (d = 1..6), G = w D^{-1} and 1 - w.
 struct Block7Consts {
     double B[7][25];
     double lu[25];
     double inv_udiag[5];
     int piv[5];
+    double W[7][25];
+    double G[25];
+    double omb;    // 1 - w
+    double omega;  // w
 };
 
 // Wavefront schedule of one sweep (see the sweep kernel for its meaning).
@@ -114,66 +120,90 @@ __device__ __forceinline__ T v7_combine(T r, T vmx, T vpx, T vmy, T vpy,
     return (r + S) / d;
 }
 
-// One block-SSOR point (the NPB-LU-shaped BLOCK7x5 operator, Sec. 7.1):
-//   s = b - sum over in-grid neighbours q of B_d x_q
-//   x = (1 - w) x_old + w D^{-1} s          (D^{-1} via the LU of B_0).
-// xq holds the neighbours by sweep direction, in the order +x, +y, +z
-// (not yet updated) and -x, -y, -z (updated); they are accumulated in that
-// order, so the values written by the sweep's previous step come last.  In a
-// backward sweep the sweep's +x is the grid's -x, so it takes the -x block.
-// Neighbours outside the grid (has[v] false) are skipped.  Every block-SSOR
-// sweep kernel calls this function.
+// One block-SSOR point (the NPB-LU-shaped BLOCK7x5 operator, Sec. 7.1),
+//   x = (1 - w) x_old + w D^{-1} (b - sum over neighbours q of B_d x_q),
+// in three parts.  Directions are taken in sweep order: the sweep's lower
+// neighbours (-x, -y, -z) already hold new values, the upper ones (+x, +y,
+// +z) old values; in a backward sweep the sweep's -x is the grid's +x, so
+// it takes the +x block.
+//   u = b - sum_{upper d} B_d x_d                     (b7_upper)
+//   g = (1 - w) x_old + G u,        G = w D^{-1}       (b7_relax)
+//   x = g - sum_{lower d} W_d x_d,  W_d = w D^{-1} B_d  (b7_lower)
+// Only the last part needs the values of the previous wavefront step.
+// Neighbours outside the grid enter as 0.  The sequential and the tiled
+// sweep kernels both call these functions, so their results agree bitwise.
+// v = 0, 1, 2 is the sweep's x, y, z direction.
 template <bool BWD>
-__device__ __forceinline__ void b7_combine(const Block7Consts &C, double w,
-                                           const double (&b)[5],
-                                           const double (&xq)[6][5],
-                                           const bool (&has)[6],
-                                           const double (&old)[5],
-                                           double (&out)[5])
+__host__ __device__ constexpr int b7_lower_dir(int v)
 {
-    double s[5];
+    return BWD ? 2 * v + 2 : 2 * v + 1;
+}
+template <bool BWD>
+__host__ __device__ constexpr int b7_upper_dir(int v)
+{
+    return BWD ? 2 * v + 1 : 2 * v + 2;
+}
+
+// Bu[v]: the block of upper direction v; xo[v]: that neighbour's values.
+// One partial sum per direction (short independent chains), subtracted in
+// the order x, y, z.
+__device__ __forceinline__ void b7_upper(const double (&Bu)[3][25],
+                                         const double (&b)[5],
+                                         const double (&xo)[3][5],
+                                         double (&u)[5])
+{
 #pragma unroll
-    for (int a = 0; a < 5; ++a) s[a] = b[a];
+    for (int a = 0; a < 5; ++a) {
+        double t[3];
 #pragma unroll
-    for (int v = 0; v < 6; ++v) {
-        // grid direction of sweep direction v: 1 -x, 2 +x, 3 -y, ..., 6 +z
-        const int d = BWD ? 2 * (v % 3) + (v < 3 ? 1 : 2)
-                          : 2 * (v % 3) + (v < 3 ? 2 : 1);
-        // a neighbour outside the grid contributes a zero operand rather
-        // than a skipped block, so that the coefficient reads stay in
-        // uniform control flow (scalar loads)
-        double xv[5];
+        for (int v = 0; v < 3; ++v) {
+            t[v] = Bu[v][5 * a] * xo[v][0];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) xv[c] = has[v] ? xq[v][c] : 0.0;
-#pragma unroll
-        for (int a = 0; a < 5; ++a)
-#pragma unroll
-            for (int c = 0; c < 5; ++c)
-                s[a] = fma(-C.B[d][5 * a + c], xv[c], s[a]);
-    }
-    // s = U^{-1} L^{-1} P s
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        const int pc = C.piv[c];
-        if (pc != c) {
-            double t = s[c];
-#pragma unroll
-            for (int q = 0; q < 5; ++q)
-                if (q == pc) { s[c] = s[q]; s[q] = t; }
+            for (int c = 1; c < 5; ++c)
+                t[v] = fma(Bu[v][5 * a + c], xo[v][c], t[v]);
         }
+        u[a] = ((b[a] - t[0]) - t[1]) - t[2];
     }
+}
+
+__device__ __forceinline__ void b7_relax(const double (&G)[25], double omb,
+                                         const double (&u)[5],
+                                         const double (&xold)[5],
+                                         double (&g)[5])
+{
 #pragma unroll
-    for (int a = 1; a < 5; ++a)
+    for (int a = 0; a < 5; ++a) {
+        double t = G[5 * a] * u[0];
 #pragma unroll
-        for (int c = 0; c < a; ++c) s[a] = fma(-C.lu[5 * a + c], s[c], s[a]);
-#pragma unroll
-    for (int a = 4; a >= 0; --a) {
-#pragma unroll
-        for (int c = a + 1; c < 5; ++c) s[a] = fma(-C.lu[5 * a + c], s[c], s[a]);
-        s[a] = s[a] * C.inv_udiag[a];
+        for (int c = 1; c < 5; ++c) t = fma(G[5 * a + c], u[c], t);
+        g[a] = fma(omb, xold[a], t);
     }
+}
+
+// Wl[v]: W of lower direction v; xn[v]: that neighbour's new values.  The
+// -x part starts from g (its value is the lane's own result of the previous
+// step); the -y and -z parts, whose values arrive last, are separate short
+// chains subtracted at the end.
+__device__ __forceinline__ void b7_lower(const double (&Wl)[3][25],
+                                         const double (&g)[5],
+                                         const double (&xn)[3][5],
+                                         double (&x)[5])
+{
 #pragma unroll
-    for (int a = 0; a < 5; ++a) out[a] = fma(w, s[a], (1.0 - w) * old[a]);
+    for (int a = 0; a < 5; ++a) {
+        double s0 = g[a];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) s0 = fma(-Wl[0][5 * a + c], xn[0][c], s0);
+        double t[2];
+#pragma unroll
+        for (int v = 1; v < 3; ++v) {
+            t[v - 1] = Wl[v][5 * a] * xn[v][0];
+#pragma unroll
+            for (int c = 1; c < 5; ++c)
+                t[v - 1] = fma(Wl[v][5 * a + c], xn[v][c], t[v - 1]);
+        }
+        x[a] = (s0 - t[0]) - t[1];
+    }
 }
 
 // Workspace (opaque in the ABI).

@@ -1,6 +1,7 @@
 """GPU parity of the BLOCK7x5 SpMV and the block SSOR half-sweeps (NPB-LU
-shaped, omega = 1.2) against the oracle, bitwise agreement between tile
-heights, and the 162^3 x 5 configuration point by point."""
+shaped, omega = 1.2) against the oracle, bitwise agreement of the tiled
+wavefront kernel with the one-thread lexicographic kernel, and the
+162^3 x 5 configuration point by point."""
 import numpy as np
 import pytest
 import torch
@@ -44,19 +45,38 @@ def test_ssor_parity(m, shape, direction):
     assert rel_inf(host(xg), ref) <= 1e-13
 
 
-def test_ssor_tile_height_bitwise(m, monkeypatch):
-    shape = (11, 9, 10)
+@pytest.mark.parametrize("shape", [(11, 9, 10), (21, 37, 19), (4, 16, 33)])
+@pytest.mark.parametrize("direction", ["fwd", "bwd", "sym"])
+def test_ssor_tiles_bitwise_vs_sequential(m, shape, direction):
+    """Several tiles along j and k with ragged tails: parity with the oracle
+    and bitwise equality with the sequential kernel."""
+    banner(f"ssor tiles {direction} {shape}")
     B = inputs.block7_blocks(4)
     A = m.block7(shape, B)
-    b = dev(inputs.standard_normal(4, shape + (5,)))
+    b = inputs.standard_normal(4, shape + (5,))
     x0 = inputs.standard_normal(5, shape + (5,))
-    outs = []
-    for nw in ("1", "2"):
-        monkeypatch.setenv("M2S_B7_WAVES", nw)
+    xg, xs = dev(x0), dev(x0)
+    m.ssor_sweep(A, dev(b), xg, 1.2, direction)
+    m.ssor_sweep_sequential(A, dev(b), xs, 1.2, direction)
+    out = host(xg)
+    assert rel_inf(out, oracle.ssor_block7(b, x0, B, 1.2, direction)) <= 1e-13
+    assert np.array_equal(out, host(xs))
+
+
+def test_ssor_omega_change_same_workspace(m):
+    """The relaxation factor is built into the device constants; a new
+    omega on the same workspace must take effect."""
+    shape = (9, 18, 7)
+    B = inputs.block7_blocks(4)
+    A = m.block7(shape, B)
+    ws = m.Workspace(A)
+    b = inputs.standard_normal(6, shape + (5,))
+    x0 = inputs.standard_normal(7, shape + (5,))
+    for w in (1.2, 0.7, 1.2):
         xg = dev(x0)
-        m.ssor_sweep(A, b, xg, 1.2, "sym")
-        outs.append(host(xg))
-    assert np.array_equal(outs[0], outs[1])
+        m.ssor_sweep(A, dev(b), xg, w, "sym", ws)
+        ref = oracle.ssor_block7(b, x0, B, w, "sym")
+        assert rel_inf(host(xg), ref) <= 1e-13
 
 
 def test_ssor_iterations_converge(m):

@@ -313,18 +313,22 @@ def test_c27_plan_matches_tile_model(shape, monkeypatch):
 
 # ---------------------------------------------------------------------------
 # Model of the tiled block-SSOR sweep kernel (7-point, 5 components): tiles
-# of 16 j by 4 nw k, rings of 8 columns, 4-column windows staged by an x and
-# a b memory wavefront per compute wavefront, and the poll wavefront.  As
-# above, but a wavefront that reads and writes one slot in one step does all
-# its reads first (the kernel orders them so), so only slots touched by two
-# different wavefronts in one step are races.
+# of 16 j by 4 k, six roles -- compute (x at the front f from g(f) and the
+# new values of the lower neighbours), upper (u at f + 2 from b and the old
+# values of the upper neighbours), relax (g at f + 1 from u and the old
+# value), x memory (stores [f - 4, f), stages x_old [f + 4, f + 8)), b
+# memory (stages b [f + 3, f + 7) and the old values of the halo rows),
+# poll.  Rings: x 16 columns, b 8, u and g 4.  Values are tracked per
+# (row, column) with all 5 components together.  As above, a slot written
+# by one wavefront in a step must not be touched by another in that step,
+# and every read a later value depends on must see the right value.
 # ---------------------------------------------------------------------------
-B7_TJ, B7_W, B7_POLL, B7_PRE = 16, 8, 4, 16
+B7_TJ, B7_KT, B7_POLL, B7_PRE = 16, 4, 2, 20
 
 
-def simulate_b7_tiles(shape, nw, zero_start=False):
+def simulate_b7_tiles(shape, zero_start=False):
     nz, ny, nx = shape
-    KT = 4 * nw
+    KT = B7_KT
     njt = -(-ny // B7_TJ)
     nbands = -(-nz // KT)
     ticket = {(jt, vt): vt * njt + jt for vt in range(nbands)
@@ -334,10 +338,17 @@ def simulate_b7_tiles(shape, nw, zero_start=False):
     def valid(j, k):
         return 0 <= j < ny and 0 <= k < nz
 
+    def live(j, k, c):
+        return valid(j, k) and 0 <= c < nx
+
     def old(j, k, c):
-        if not valid(j, k) or not 0 <= c < nx or zero_start:
-            return 0
-        return ("old", j, k, c)
+        return ("old", j, k, c) if live(j, k, c) and not zero_start else 0
+
+    def new(j, k, c):
+        return ("new", j, k, c) if live(j, k, c) else 0
+
+    def bval(j, k, c):
+        return ("b", j, k, c) if live(j, k, c) else 0
 
     for vt in range(nbands):
         for jt in range(njt):
@@ -346,44 +357,39 @@ def simulate_b7_tiles(shape, nw, zero_start=False):
             T_start = T0 - 1 - B7_PRE
             T_lastc = T0 + (B7_TJ - 1) + (KT - 1) + nx - 1
             nblk = (T_lastc + 5 - T_start + 15) // 16
-            xr, rr = {}, {}
-
-            def xs(kq, jq, c):
-                return ("x", (kq + 1, jq + 1), c % B7_W)
-
+            mem = {}
             for step in range(16 * nblk):
                 T = T_start + step
-                p4 = step % 4
+                p = step % 4
+                # loads are parked 8 steps (two services of the plane)
+                first = T - 8 < T_start
                 writes, reads = [], []
-                for m in range(nw):
-                    kk = 4 * m + p4
-                    wx, wb = nw + m, 2 * nw + m
-                    for e in range(320):
-                        jj, cq = e // 20, (e % 20) // 5
-                        j, k = j0 + jj, k0 + kk
-                        f = T - (j + k)
-                        cs, cx, cr = f - 4 + cq, f + 2 + cq, f + 1 + cq
-                        if valid(j, k) and 0 <= cs < nx:
-                            reads.append((xs(kk, jj, cs), wx,
-                                          ("new", j, k, cs)))
-                            stored[(k, j, cs)] = stored.get((k, j, cs), 0) + 1
-                        vx = 0 if T - 4 < T_start else old(j, k, cx)
-                        writes.append((xs(kk, jj, cx), vx, wx))
-                        vr = (0 if T - 4 < T_start or not valid(j, k) or
-                              not 0 <= cr < nx else ("r", j, k, cr))
-                        writes.append((("r", (kk, jj), cr % B7_W), vr, wb))
-                    for e in range(128):
-                        isa = e < 20
-                        if not (isa or (m == nw - 1 and e < 100)):
-                            continue
-                        jj = 16 if isa else 4 * p4 + (e - 20) // 20
-                        o = e if isa else (e - 20) % 20
-                        kq = kk if isa else KT
-                        j, k = j0 + jj, k0 + kq
-                        cx = T - (j + k) + 2 + o // 5
-                        vh = 0 if T - 4 < T_start else old(j, k, cx)
-                        writes.append((xs(kq, jj, cx), vh, wb))
-                wp = 3 * nw
+                # memory wavefronts, plane p
+                for e in range(320):
+                    jj, cq = e // 20, (e % 20) // 5
+                    j, k = j0 + jj, k0 + p
+                    f = T - (j + k)
+                    cs = f - 4 + cq
+                    if live(j, k, cs):
+                        reads.append((("x", p, jj, cs % 16), "mx",
+                                      ("new", j, k, cs)))
+                        stored[(k, j, cs)] = stored.get((k, j, cs), 0) + 1
+                    cx = f + 4 + cq
+                    writes.append((("x", p, jj, cx % 16),
+                                   0 if first else old(j, k, cx), "mx"))
+                    cb = f + 3 + cq
+                    writes.append((("b", p, jj, cb % 8),
+                                   0 if first else bval(j, k, cb), "mb"))
+                for e in range(100):
+                    isa = e < 20
+                    hjj = 16 if isa else 4 * p + (e - 20) // 20
+                    o = e if isa else (e - 20) % 20
+                    hkk = p if isa else KT
+                    hj, hk = j0 + hjj, k0 + hkk
+                    ch = T - (hj + hk) + 4 + o // 5
+                    writes.append((("x", hkk, hjj, ch % 16),
+                                   0 if first else old(hj, hk, ch), "mb"))
+                # poll
                 for e in range(5 * (KT + 16)):
                     h = e // 5
                     left = h < KT
@@ -404,34 +410,40 @@ def simulate_b7_tiles(shape, nw, zero_start=False):
                         v = ("new", j, k, c)
                     else:
                         v = 0
-                    writes.append((xs(kk, jj, c), v, wp))
-                for w in range(nw):
-                    for lane in range(64):
-                        jj, kk = lane & 15, 4 * w + (lane >> 4)
-                        j, k = j0 + jj, k0 + kk
-                        if not valid(j, k):
-                            continue
-                        f = T - (j + k)
-                        if not 0 <= f < nx:
-                            continue
-                        # neighbours that exist (has[]), own old at f, f+1
-                        nb = [((jj - 1, kk), j - 1 >= 0, True),
-                              ((jj, kk - 1), k - 1 >= 0, True),
-                              ((jj + 1, kk), j + 1 < ny, False),
-                              ((jj, kk + 1), k + 1 < nz, False)]
-                        for (jq, kq), ex, lower in nb:
-                            if ex:
-                                jn, kn = j0 + jq, k0 + kq
-                                e_ = (("new", jn, kn, f) if lower
-                                      else old(jn, kn, f))
-                                reads.append((xs(kq, jq, f), w, e_))
-                        reads.append((xs(kk, jj, f), w, old(j, k, f)))
-                        if f + 1 < nx:
-                            reads.append((xs(kk, jj, f + 1), w,
-                                          old(j, k, f + 1)))
-                        reads.append((("r", (kk, jj), f % B7_W), w,
-                                      ("r", j, k, f)))
-                        writes.append((xs(kk, jj, f), ("new", j, k, f), w))
+                    writes.append((("x", kk, jj, c % 16), v, "pl"))
+                # the three arithmetic roles, lane = row (jj, kk)
+                for lane in range(64):
+                    jj, kk = lane & 15, lane >> 4
+                    j, k = j0 + jj, k0 + kk
+                    f = T - (j + k)
+                    c = f + 2                       # upper
+                    if live(j, k, c):
+                        reads += [
+                            (("b", kk, jj, c % 8), "hu", bval(j, k, c)),
+                            (("x", kk, jj, (c + 1) % 16), "hu",
+                             old(j, k, c + 1)),
+                            (("x", kk, jj + 1, c % 16), "hu", old(j + 1, k, c)),
+                            (("x", kk + 1, jj, c % 16), "hu", old(j, k + 1, c))]
+                    writes.append((("u", kk, jj, c % 4),
+                                   ("u", j, k, c) if live(j, k, c) else "junk",
+                                   "hu"))
+                    c = f + 1                       # relax
+                    if live(j, k, c):
+                        reads += [
+                            (("u", kk, jj, c % 4), "hg", ("u", j, k, c)),
+                            (("x", kk, jj, c % 16), "hg", old(j, k, c))]
+                    writes.append((("g", kk, jj, c % 4),
+                                   ("g", j, k, c) if live(j, k, c) else "junk",
+                                   "hg"))
+                    if live(j, k, f):               # compute
+                        reads += [
+                            (("g", kk, jj, f % 4), "cp", ("g", j, k, f)),
+                            (("x", kk, jj - 1, f % 16), "cp",
+                             new(j - 1, k, f)),
+                            (("x", kk - 1, jj, f % 16), "cp",
+                             new(j, k - 1, f))]
+                        writes.append((("x", kk, jj, f % 16),
+                                       ("new", j, k, f), "cp"))
                 wsl = {}
                 for slot, v, w in writes:
                     prev = wsl.get(slot)
@@ -440,11 +452,10 @@ def simulate_b7_tiles(shape, nw, zero_start=False):
                 for slot, w, e_ in reads:
                     if slot in wsl:
                         assert wsl[slot][1] == w, ("read/write race", slot, T)
-                    mem = xr if slot[0] == "x" else rr
-                    got = mem.get(slot[1:], 0)
+                    got = mem.get(slot, 0)
                     assert got == e_, (T, slot, got, e_)
                 for slot, (v, w) in wsl.items():
-                    (xr if slot[0] == "x" else rr)[slot[1:]] = v
+                    mem[slot] = v
     for k in range(nz):
         for j in range(ny):
             for i in range(nx):
@@ -453,31 +464,28 @@ def simulate_b7_tiles(shape, nw, zero_start=False):
 
 
 @pytest.mark.parametrize("shape", [(9, 7, 6), (5, 20, 11), (13, 17, 3),
-                                   (1, 1, 1), (4, 33, 5)])
-@pytest.mark.parametrize("nw", [1, 2])
-def test_b7_tile_model(shape, nw):
-    simulate_b7_tiles(shape, nw)
+                                   (1, 1, 1), (4, 33, 5), (11, 16, 8)])
+def test_b7_tile_model(shape):
+    simulate_b7_tiles(shape)
 
 
 def test_b7_tile_model_zero_start():
-    simulate_b7_tiles((6, 9, 5), 1, zero_start=True)
+    simulate_b7_tiles((6, 9, 5), zero_start=True)
 
 
-def b7_tile_count(shape, nw):
+def b7_tile_count(shape):
     nz, ny, nx = shape
-    return -(-ny // B7_TJ) * -(-nz // (4 * nw))
+    return -(-ny // B7_TJ) * -(-nz // B7_KT)
 
 
 @pytest.mark.parametrize("shape", [(9, 7, 6), (16, 16, 16), (13, 40, 9)])
-def test_b7_plan_matches_tile_model(shape, monkeypatch):
+def test_b7_plan_matches_tile_model(shape):
     import paper_2204_13304_amd as m
-    for nw in (1, 2):
-        monkeypatch.setenv("M2S_B7_WAVES", str(nw))
-        p = m.plan_sweep(m.block7(shape, np.eye(5)[None].repeat(7, 0) * 10))
-        assert p["slab_planes"] == 4 * nw
-        # nw compute + 2 nw memory wavefronts + 1 poll wavefront
-        assert p["threads"] == 64 * (3 * nw + 1)
-        assert p["nslabs"] == b7_tile_count(shape, nw)
+    p = m.plan_sweep(m.block7(shape, np.eye(5)[None].repeat(7, 0) * 10))
+    assert p["slab_planes"] == B7_KT
+    # compute, upper, relax, x memory, poll, b memory
+    assert p["threads"] == 64 * 6
+    assert p["nslabs"] == b7_tile_count(shape)
 
 
 # ---------------------------------------------------------------------------
