@@ -31,7 +31,8 @@ Also reported on the same line:
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 2]
     python bench.py --roofline-only      (kernel loops only, for profiling)
-    python bench.py --workloads-only     (the block SSOR and VAR7 runs only)
+    python bench.py --workloads-only [--workloads ssor|var7]
+                                         (the block SSOR and VAR7 runs only)
 """
 from __future__ import annotations
 
@@ -45,23 +46,27 @@ import time
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
 SWEEP_PROFILE = os.path.join(ROOT, "profiles", "c27_sweep_256.md")
+SSOR_PROFILE = os.path.join(ROOT, "profiles", "b7_ssor_162.md")
 
 
 def measured_traffic(profile=SWEEP_PROFILE):
-    """HBM bytes per launch of the sweep kernel from the committed rocprofv3
-    counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
-    the kernel source has changed since those counters were taken."""
+    """HBM bytes per launch of a kernel from a committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when any of
+    the sources the kernel is built from has changed since those counters
+    were taken."""
     try:
         fields = {}
         with open(profile) as fh:
             for line in fh:
                 k, _, v = line.partition(":")
-                if k.strip() in ("kernel_source", "kernel_source_sha256",
+                if k.strip() in ("kernel_sources", "kernel_sources_sha256",
                                  "traffic_bytes_per_launch"):
                     fields[k.strip()] = v.strip()
-        with open(os.path.join(ROOT, fields["kernel_source"]), "rb") as fh:
-            digest = hashlib.sha256(fh.read()).hexdigest()
-        if digest != fields["kernel_source_sha256"]:
+        h = hashlib.sha256()
+        for src in fields["kernel_sources"].split(","):
+            with open(os.path.join(ROOT, src.strip()), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != fields["kernel_sources_sha256"]:
             return None
         return int(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -85,6 +90,8 @@ def parse():
                     help="skip the block SSOR and VAR7 workloads")
     ap.add_argument("--workloads-only", action="store_true",
                     help="only the block SSOR and VAR7 workloads")
+    ap.add_argument("--workloads", default="ssor,var7",
+                    help="which of them: ssor, var7 (comma-separated)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the kernel loops and a copy calibration")
     return ap.parse_args()
@@ -109,8 +116,17 @@ def flops_per_iteration(n, levels):
     return f
 
 
-def extra_workloads(torch, m, inputs, dev, reps):
+def extra_workloads(torch, m, inputs, dev, reps, which=("ssor", "var7")):
     """Block SSOR (162^3 x 5) and the VAR7 solve with its gradient (128^3)."""
+    out = {}
+    if "ssor" in which:
+        out.update(ssor_workload(torch, m, inputs, dev, reps))
+    if "var7" in which:
+        out.update(var7_workload(torch, m, inputs, dev, reps))
+    return out
+
+
+def ssor_workload(torch, m, inputs, dev, reps):
     f64 = torch.float64
     out = {}
     n = 162
@@ -123,26 +139,30 @@ def extra_workloads(torch, m, inputs, dev, reps):
     m.ssor_sweep(A, b, x, 1.2, "sym", ws)  # warm
     x.zero_()
     iters = 20
+    # one SSOR iteration = a forward and a backward half-sweep kernel
+    # (out of place into the workspace and back, no copies)
     ms = event_ms(torch, lambda: m.ssor_sweep(A, b, x, 1.2, "sym", ws), iters)
     ws.check()
     err = (x - 1.0).abs().max().item()
-    fwd = event_ms(torch, lambda: m.ssor_sweep(A, b, x, 1.2, "fwd", ws), reps)
-    bwd = event_ms(torch, lambda: m.ssor_sweep(A, b, x, 1.2, "bwd", ws), reps)
-    ws.check()
-    half = 0.5 * (fwd + bwd)
+    half = 0.5 * ms
     gbs = 120 * n ** 3 / (half * 1e-3) / 1e9
     out["block_ssor"] = {
         "workload": "block7 162^3 x 5, blocks seed 4, omega 1.2, b = A*1, "
                     "x0 = 0, 20 iterations (forward + backward)",
         "seconds_20_iterations": ms * iters * 1e-3,
         "max_abs_err_vs_ones": err,
-        "half_sweep_ms": half, "fwd_ms": fwd, "bwd_ms": bwd,
-        "achieved": gbs, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+        "half_sweep_ms": half,
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(SSOR_PROFILE)},
         "kernel": "b7_tile_kernel (fwd and bwd), 120 B/point"}
     log(f"block SSOR 162^3x5: 20 iterations {ms * iters:.1f} ms, half-sweep "
         f"{half:.3f} ms ({gbs:.0f} GB/s), |x - 1| {err:.2e}")
-    del A, ws, b, x, ones
+    return out
 
+
+def var7_workload(torch, m, inputs, dev, reps):
+    out = {}
     n = 128
     shape = (n, n, n)
     P = inputs.var7_problem(5, shape)
@@ -256,8 +276,8 @@ def main():
     shape = (n, n, n)
 
     if args.workloads_only:
-        print(json.dumps({"workloads": extra_workloads(torch, m, inputs, dev,
-                                                       args.reps)}))
+        print(json.dumps({"workloads": extra_workloads(
+            torch, m, inputs, dev, args.reps, args.workloads.split(","))}))
         return 0
 
     log(f"roofline loops at {n}^3, {args.reps} launches each")
@@ -332,7 +352,8 @@ def main():
 
     extra = None
     if not args.no_extra:
-        extra = extra_workloads(torch, m, inputs, dev, args.reps)
+        extra = extra_workloads(torch, m, inputs, dev, args.reps,
+                                args.workloads.split(","))
 
     cpu = None
     if not args.no_cpu:
