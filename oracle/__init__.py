@@ -68,6 +68,10 @@ def _load():
         g("lu5_factor").argtypes = [P, P, np.ctypeslib.ndpointer(
             dtype=np.int32, flags="C_CONTIGUOUS")]
         g("lu5_factor").restype = i
+        g("jacobi9").argtypes = [i, i, R, R, P, P, i, P]
+        g("ilu27_factor").argtypes = [i, i, i, R, R, P]
+        g("ilu27_solve").argtypes = [i, i, i, R, P, P, P]
+        g("penta_lines").argtypes = [i, i, i, i, P, P, P]
     lib.m2so_pcg.restype = i
     lib.m2so_pcg.argtypes = [i, i, i, i, d, d, C.c_void_p, C.c_void_p,
                              C.c_void_p, i, i, _dp, _dp, i, d, i,
@@ -285,6 +289,46 @@ class MG:
 
 
 # ---------------------------------------------------------------- PCG
+# ------------------------------------------- microbenchmarks, Sec. 7.2.1
+def jacobi9(b, x0, iters, diag=8.0, off=-1.0, dtype=np.float64):
+    """iters Jacobi iterations of the 2-D 9-point operator (diag on the
+    diagonal, off on the 8 neighbours, Dirichlet) on b, x0 of shape (ny, nx);
+    returns x_iters."""
+    b = _c(b, dtype)
+    x = _c(x0, dtype).copy()
+    ny, nx = b.shape
+    _fn("jacobi9", dtype)(nx, ny, diag, off, b, x, int(iters), np.empty_like(x))
+    return x
+
+
+def ilu27_factor(shape, diag=26.0, off=-1.0, dtype=np.float64):
+    """Factor diagonal d of the 27-point ILU M = (D + L) D^{-1} (D + U)."""
+    nz, ny, nx = shape
+    d = np.empty(shape, dtype=dtype)
+    _fn("ilu27_factor", dtype)(nx, ny, nz, diag, off, d)
+    return d
+
+
+def ilu27_solve(d, r, off=-1.0, dtype=np.float64):
+    """z = M^{-1} r (lower solve p ascending, then upper solve p descending)."""
+    d, r = _c(d, dtype), _c(r, dtype)
+    nz, ny, nx = r.shape
+    z = np.empty_like(r)
+    _fn("ilu27_solve", dtype)(nx, ny, nz, off, d, r, z)
+    return z
+
+
+def penta_lines(coef, r, axis, dtype=np.float64):
+    """Solve the pentadiagonal systems along every grid line of `axis`
+    ("x", "y" or "z"); coef has shape (5, nz, ny, nx) = bands a..e."""
+    coef, r = _c(coef, dtype), _c(r, dtype)
+    nz, ny, nx = r.shape
+    x = np.empty_like(r)
+    _fn("penta_lines", dtype)(nx, ny, nz, {"x": 0, "y": 1, "z": 2}[axis], coef,
+                              r, x)
+    return x
+
+
 def pcg(b, x0=None, kind="const27", precond="mg", levels=4, faces=None,
         diag=26.0, off=-1.0, max_iter=50, tol=0.0, replace_every=0):
     """HPCG-form preconditioned CG in double.

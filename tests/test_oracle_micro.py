@@ -1,0 +1,153 @@
+"""Pins of the oracle's microbenchmark routines (Sec. 7.2.1: Jacobi
+iterations of a 2-D 9-point stencil, the 27-point ILU) and of its
+pentadiagonal line solves (the SP-shaped systems of Sec. 7.1), against
+closed forms, fixed points, defining properties and library routines
+(scipy.sparse, scipy.linalg.solve_banded) -- never against a retyping of
+the oracle's own loops."""
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle
+
+
+def _tri_ones(n):
+    return sp.diags([np.ones(n - 1), np.ones(n), np.ones(n - 1)], [-1, 0, 1])
+
+
+def _A9(ny, nx, diag=8.0, off=-1.0):
+    """2-D 9-point operator as a sparse matrix: the neighbour sum of the
+    3x3 box minus the centre is (T_y kron T_x - I)."""
+    T = sp.kron(_tri_ones(ny), _tri_ones(nx)).tocsr()
+    return (diag * sp.identity(nx * ny) + off * (T - sp.identity(nx * ny))).tocsr()
+
+
+def _A27(nz, ny, nx, diag=26.0, off=-1.0):
+    T = sp.kron(sp.kron(_tri_ones(nz), _tri_ones(ny)), _tri_ones(nx)).tocsr()
+    n = nx * ny * nz
+    return (diag * sp.identity(n) + off * (T - sp.identity(n))).tocsr()
+
+
+# ------------------------------------------------------------- Jacobi
+def test_jacobi9_one_step_from_zero():
+    b = np.random.default_rng(0).standard_normal((9, 13))
+    x = oracle.jacobi9(b, np.zeros_like(b), 1)
+    assert np.array_equal(x, b / 8.0)
+
+
+def test_jacobi9_fixed_point():
+    ny, nx = 11, 17
+    b = (_A9(ny, nx) @ np.ones(nx * ny)).reshape(ny, nx)
+    x = oracle.jacobi9(b, np.ones((ny, nx)), 5)
+    assert np.max(np.abs(x - 1)) <= 1e-15
+
+
+@pytest.mark.parametrize("shape", [(7, 9), (1, 12), (16, 5)])
+def test_jacobi9_against_sparse_matrix(shape):
+    ny, nx = shape
+    rng = np.random.default_rng(1)
+    b = rng.standard_normal(shape)
+    x0 = rng.standard_normal(shape)
+    A = _A9(ny, nx)
+    D = A.diagonal()
+    x = x0.ravel().copy()
+    for _ in range(6):
+        x = x + (b.ravel() - A @ x) / D
+    got = oracle.jacobi9(b, x0, 6)
+    assert np.max(np.abs(got.ravel() - x)) <= 1e-13 * max(1, np.abs(x).max())
+
+
+def test_jacobi9_converges_to_solution():
+    ny, nx = 12, 12
+    b = (_A9(ny, nx) @ np.ones(nx * ny)).reshape(ny, nx)
+    e50 = np.abs(oracle.jacobi9(b, np.zeros_like(b), 50) - 1).max()
+    e200 = np.abs(oracle.jacobi9(b, np.zeros_like(b), 200) - 1).max()
+    assert e200 < e50 < 1
+
+
+# ---------------------------------------------------------------- ILU
+@pytest.mark.parametrize("shape", [(3, 4, 5), (2, 6, 3), (4, 4, 4)])
+def test_ilu27_diagonal_of_factor_matches_operator(shape):
+    nz, ny, nx = shape
+    A = _A27(nz, ny, nx)
+    d = oracle.ilu27_factor(shape).ravel()
+    L, U, D = sp.tril(A, -1), sp.triu(A, 1), sp.diags(d)
+    M = ((D + L) @ sp.diags(1.0 / d) @ (D + U)).toarray()
+    assert np.max(np.abs(np.diag(M) - 26.0)) <= 1e-13
+    # off the diagonal M = A + L D^-1 U
+    Mo = A.toarray() + (L @ sp.diags(1.0 / d) @ U).toarray()
+    np.fill_diagonal(Mo, 0.0)
+    M0 = M.copy()
+    np.fill_diagonal(M0, 0.0)
+    assert np.max(np.abs(M0 - Mo)) <= 1e-14
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 5), (5, 3, 2)])
+def test_ilu27_solve_inverts_factor(shape):
+    nz, ny, nx = shape
+    A = _A27(nz, ny, nx)
+    d = oracle.ilu27_factor(shape)
+    r = np.random.default_rng(2).standard_normal(shape)
+    z = oracle.ilu27_solve(d, r).ravel()
+    dv = d.ravel()
+    L, U, D = sp.tril(A, -1), sp.triu(A, 1), sp.diags(dv)
+    Mz = (D + L) @ ((D + U) @ z / dv)
+    assert np.max(np.abs(Mz - r.ravel())) <= 1e-13
+
+
+def test_ilu27_is_exact_on_a_line():
+    # one grid line: the 27-point operator is tridiagonal and its ILU the
+    # exact LU factorisation
+    shape = (1, 1, 23)
+    A = _A27(*shape)
+    d = oracle.ilu27_factor(shape)
+    r = np.random.default_rng(3).standard_normal(shape)
+    z = oracle.ilu27_solve(d, r).ravel()
+    ref = spla.spsolve(A.tocsc(), r.ravel())
+    assert np.max(np.abs(z - ref)) <= 1e-14 * np.abs(ref).max()
+
+
+# -------------------------------------------------- pentadiagonal lines
+def _penta(shape, seed):
+    rng = np.random.default_rng(seed)
+    coef = rng.uniform(-1.0, 1.0, (5,) + shape)
+    coef[2] += 6.0  # diagonally dominant
+    return coef, rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("axis", ["x", "y", "z"])
+@pytest.mark.parametrize("shape", [(4, 5, 6), (1, 1, 9), (7, 3, 2)])
+def test_penta_lines_against_solve_banded(axis, shape):
+    coef, r = _penta(shape, 4)
+    x = oracle.penta_lines(coef, r, axis)
+    ax = {"x": 2, "y": 1, "z": 0}[axis]
+    c = np.moveaxis(coef, ax + 1, -1)
+    rr = np.moveaxis(r, ax, -1)
+    xx = np.moveaxis(x, ax, -1)
+    n = rr.shape[-1]
+    for idx in np.ndindex(rr.shape[:-1]):
+        a, b, cc, d, e = (c[(k,) + idx] for k in range(5))
+        ab = np.zeros((5, n))
+        # solve_banded: ab[u + i - j, j] = A[i, j], u = 2
+        ab[0, 2:] = e[:-2]
+        ab[1, 1:] = d[:-1]
+        ab[2, :] = cc
+        ab[3, :-1] = b[1:]
+        ab[4, :-2] = a[2:]
+        ref = scipy.linalg.solve_banded((2, 2), ab, rr[idx])
+        assert np.max(np.abs(xx[idx] - ref)) <= 1e-13 * max(1, np.abs(ref).max())
+
+
+def test_penta_lines_residual():
+    shape = (3, 4, 11)
+    coef, r = _penta(shape, 5)
+    x = oracle.penta_lines(coef, r, "x")
+    a, b, c, d, e = coef
+    res = c * x
+    res[..., 1:] += b[..., 1:] * x[..., :-1]
+    res[..., 2:] += a[..., 2:] * x[..., :-2]
+    res[..., :-1] += d[..., :-1] * x[..., 1:]
+    res[..., :-2] += e[..., :-2] * x[..., 2:]
+    assert np.max(np.abs(res - r)) <= 1e-13
