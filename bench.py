@@ -90,8 +90,8 @@ def parse():
                     help="skip the block SSOR and VAR7 workloads")
     ap.add_argument("--workloads-only", action="store_true",
                     help="only the block SSOR and VAR7 workloads")
-    ap.add_argument("--workloads", default="ssor,var7",
-                    help="which of them: ssor, var7 (comma-separated)")
+    ap.add_argument("--workloads", default="ssor,var7,jacobi",
+                    help="which of them: ssor, var7, jacobi (comma-separated)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the kernel loops and a copy calibration")
     return ap.parse_args()
@@ -116,14 +116,47 @@ def flops_per_iteration(n, levels):
     return f
 
 
-def extra_workloads(torch, m, inputs, dev, reps, which=("ssor", "var7")):
+def extra_workloads(torch, m, inputs, dev, reps,
+                    which=("ssor", "var7", "jacobi")):
     """Block SSOR (162^3 x 5) and the VAR7 solve with its gradient (128^3)."""
     out = {}
     if "ssor" in which:
         out.update(ssor_workload(torch, m, inputs, dev, reps))
     if "var7" in which:
         out.update(var7_workload(torch, m, inputs, dev, reps))
+    if "jacobi" in which:
+        out.update(jacobi_workload(torch, m, inputs, dev, reps))
     return out
+
+
+def jacobi_workload(torch, m, inputs, dev, reps):
+    """JacIter (Sec. 7.2.1): 64 Jacobi iterations of the 2-D 9-point
+    operator on 4096^2, FP64, temporally blocked (8 iterations per pass)
+    and unblocked."""
+    n, T = 4096, 64
+    b = torch.from_numpy(inputs.standard_normal(33, (n, n))).to(dev)
+    x = torch.zeros_like(b)
+    tmp = torch.empty_like(b)
+    res = {}
+    for tb in (8, 1):
+        m.jacobi9(b, x, T, tblock=tb, tmp=tmp)
+        ms = event_ms(torch, lambda: m.jacobi9(b, x, T, tblock=tb, tmp=tmp),
+                      max(1, reps // 3))
+        res[tb] = ms
+    pts = n * n * T
+    eff = 24 * pts / (res[8] * 1e-3) / 1e9
+    log(f"jacobi9 {n}^2 x {T}: {res[8]:.3f} ms (blocked 8), "
+        f"{res[1]:.3f} ms (unblocked); {pts / (res[8] * 1e-3) / 1e9:.0f} "
+        f"Gpoint-iterations/s")
+    return {"jacobi9": {
+        "workload": f"2-D 9-point Jacobi (diag 8, off -1), {n}^2, {T} "
+                    "iterations, FP64, b ~ N(0,1) seed 33, x0 = 0",
+        "ms": res[8], "ms_unblocked": res[1],
+        "gpoint_iterations_per_s": pts / (res[8] * 1e-3) / 1e9,
+        "effective_gbs": eff,
+        "effective_unit": "GB/s of the unblocked traffic (24 B per point and "
+                          "iteration: read x and b, write x)",
+        "frac_vs_hbm_peak": eff / HBM_PEAK_GBS}}
 
 
 def ssor_workload(torch, m, inputs, dev, reps):

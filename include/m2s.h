@@ -281,6 +281,22 @@ m2s_status m2s_convert(const void *src, m2s_dtype src_t, void *dst,
                        m2s_dtype dst_t, int64_t n, hipStream_t stream);
 
 /* ---------------------------------------------------------------------
+ * Jacobi iterations of the 2-D 9-point operator (the JacIter
+ * microbenchmark of Sec. 7.2.1): on an nx x ny grid ([ny][nx], x fastest,
+ * F64), iters times
+ *   x_p <- (b_p - off * sum_{q in N8(p)} x_q) / diag,
+ * all points at once from the previous iterate; values outside the grid
+ * are 0 (Dirichlet).  x: in x_0, out x_iters; b read-only; tmp: a second
+ * nx*ny-double device buffer owned by the caller (overwritten).  tblock
+ * (1, 2, 4 or 8): iterations fused per pass over memory (temporal blocking
+ * in LDS; the result does not depend on it beyond rounding order).  x, b
+ * and tmp must not overlap; nx*ny < 2^31; diag != 0.
+ * --------------------------------------------------------------------- */
+m2s_status m2s_jacobi9(int32_t nx, int32_t ny, double diag, double off,
+                       const double *b, double *x, double *tmp, int32_t iters,
+                       int32_t tblock, hipStream_t stream);
+
+/* ---------------------------------------------------------------------
  * Schedule of the wavefront sweep (host only, no GPU needed), exposed so
  * the schedule's legality (every dependence from a strictly earlier step)
  * can be checked on the CPU.  Point (i, j, k) runs at step

@@ -293,6 +293,24 @@ def pcg_solve(A: Stencil, b, x=None, precond="mg", mg: MG | None = None,
     return x, out
 
 
+def jacobi9(b, x, iters, tblock=8, diag=8.0, off=-1.0, tmp=None):
+    """iters Jacobi iterations of the 2-D 9-point operator on x (ny, nx),
+    in place; tblock iterations fused per pass over memory."""
+    lib = L.load()
+    if b.dim() != 2:
+        raise ValueError("jacobi9 takes 2-D fields (ny, nx)")
+    _need(b, torch.float64, tuple(b.shape), "b")
+    _need(x, torch.float64, tuple(b.shape), "x")
+    if tmp is None:
+        tmp = torch.empty_like(x)
+    _need(tmp, torch.float64, tuple(b.shape), "tmp")
+    ny, nx = b.shape
+    L.check(lib.m2s_jacobi9(nx, ny, float(diag), float(off), _ptr(b), _ptr(x),
+                            _ptr(tmp), int(iters), int(tblock), _stream()),
+            "m2s_jacobi9")
+    return x
+
+
 def face_grad(A: Stencil, u, lam):
     lib = L.load()
     nz, ny, nx = A.shape

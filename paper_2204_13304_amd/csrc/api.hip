@@ -627,6 +627,24 @@ m2s_status m2s_ssor_sweep_sequential(const m2s_stencil *A, const void *b,
     return M2S_OK;
 }
 
+m2s_status m2s_jacobi9(int32_t nx, int32_t ny, double diag, double off,
+                       const double *b, double *x, double *tmp, int32_t iters,
+                       int32_t tblock, hipStream_t stream)
+{
+    if (!b || !x || !tmp || iters < 0 || !(diag != 0.0) ||
+        !std::isfinite(diag) || !std::isfinite(off))
+        return M2S_ERR_ARG;
+    if (tblock != 1 && tblock != 2 && tblock != 4 && tblock != 8)
+        return M2S_ERR_ARG;
+    if (nx < 1 || ny < 1 || (int64_t)nx * ny >= ((int64_t)1 << 31))
+        return M2S_ERR_SHAPE;
+    const size_t vb = sizeof(double) * (size_t)nx * (size_t)ny;
+    if (overlap(b, x, vb) || overlap(b, tmp, vb) || overlap(x, tmp, vb))
+        return M2S_ERR_ALIAS;
+    return hip_status(
+        launch_jacobi9(nx, ny, diag, off, b, x, tmp, iters, tblock, stream));
+}
+
 m2s_status m2s_face_grad(const m2s_stencil *A, const double *u,
                          const double *lam, double *gkx, double *gky,
                          double *gkz, hipStream_t stream)

@@ -1,0 +1,163 @@
+// k_jacobi.hip -- Jacobi iterations of the 2-D 9-point operator (the JacIter
+// microbenchmark of Sec. 7.2.1), temporally blocked for gfx950.
+//
+// One iteration is x_{t+1} = (b - off * N8 x_t) / diag on an nx x ny grid
+// (Dirichlet: values outside the grid are 0).  A Jacobi stencil has no
+// spatial dependence, only the temporal one, so H iterations can be fused
+// in LDS: a workgroup loads x and b on a (64 + 2H)^2 region around its
+// 64 x 64 output tile, runs the H iterations on regions that shrink by one
+// cell per side each time (the halo is recomputed by the neighbouring
+// tiles, overlapped tiling), and writes the tile.  HBM traffic per pass is
+// about 2 (64 + 2H)^2 + 64^2 values per 64^2 points, i.e. per iteration
+// (24 + 32 H / 64 + ...) / H bytes per point instead of 24.
+//
+// Each thread owns one column of the region and a contiguous range of its
+// rows; it walks down the rows keeping the three-value row sums of the
+// previous and current row in registers, so a point costs three LDS reads.
+// One workgroup per CU (the two iterate buffers and b fill the LDS).
+#include "m2s_internal.hpp"
+
+#include <algorithm>
+
+namespace m2s {
+
+constexpr int J9_TS = 64;    // output tile edge
+constexpr int J9_NT = 1024;  // threads per workgroup: 16 wavefronts hide the
+                             // LDS and load latency of the short row walks
+
+template <int H>
+__global__ void __launch_bounds__(J9_NT)
+    jacobi9_tb_kernel(int nx, int ny, double inv_diag, double off,
+                      const double *__restrict__ b,
+                      const double *__restrict__ xin,
+                      double *__restrict__ xout)
+{
+    constexpr int W = J9_TS + 2 * H;
+    constexpr int G = J9_NT / W;  // row groups
+    extern __shared__ double sm[];
+    double *const xa = sm;
+    double *const xb = sm + W * W;
+    double *const bs = sm + 2 * W * W;
+    const int gx0 = blockIdx.x * J9_TS - H, gy0 = blockIdx.y * J9_TS - H;
+    const int tid = threadIdx.x;
+
+    // all of a thread's loads first (many in flight), then the LDS stores
+    constexpr int NL = (W * W + J9_NT - 1) / J9_NT;
+    double vx[NL], vb[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int e = tid + q * J9_NT;
+        const int ly = e / W, lx = e - (e / W) * W;
+        const int gx = gx0 + lx, gy = gy0 + ly;
+        const bool in =
+            e < W * W && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        const long g = in ? (long)gy * nx + gx : 0;
+        vx[q] = in ? xin[g] : 0.0;
+        vb[q] = in ? b[g] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int e = tid + q * J9_NT;
+        if (e < W * W) {
+            xa[e] = vx[q];
+            bs[e] = vb[q];
+        }
+    }
+    __syncthreads();
+
+    const int c = tid % W, grp = tid / W;
+    const int gx = gx0 + c;
+    const bool colin = gx >= 0 && gx < nx;
+#pragma unroll 1
+    for (int t = 1; t <= H; ++t) {
+        const double *src = (t & 1) ? xa : xb;
+        double *dst = (t & 1) ? xb : xa;
+        const int lo = t, hi = W - t;  // rows and columns computed
+        const int rows = (hi - lo + G - 1) / G;
+        const int r0 = lo + grp * rows, r1 = min(hi, r0 + rows);
+        if (grp < G && c >= lo && c < hi && r0 < r1) {
+            auto row3 = [&](int r, double &s3, double &side) {
+                const double *q = src + r * W + c;
+                const double l = q[-1], m = q[0], rr = q[1];
+                side = l + rr;
+                s3 = side + m;
+            };
+            double sp, spd, sc, scd;
+            row3(r0 - 1, sp, spd);
+            row3(r0, sc, scd);
+#pragma unroll 4
+            for (int r = r0; r < r1; ++r) {
+                double sn, snd;
+                row3(r + 1, sn, snd);
+                const double sum = (sp + scd) + sn;
+                const int gy = gy0 + r;
+                const bool in = colin && gy >= 0 && gy < ny;
+                dst[r * W + c] = in ? (bs[r * W + c] - off * sum) * inv_diag
+                                    : 0.0;
+                sp = sc;
+                sc = sn;
+                scd = snd;
+            }
+        }
+        __syncthreads();
+    }
+
+    const double *fin = (H & 1) ? xb : xa;
+    for (int e = tid; e < J9_TS * J9_TS; e += J9_NT) {
+        const int ly = e / J9_TS, lx = e % J9_TS;
+        const int ox = gx0 + H + lx, oy = gy0 + H + ly;
+        if (ox < nx && oy < ny)
+            xout[(long)oy * nx + ox] = fin[(ly + H) * W + lx + H];
+    }
+}
+
+template <int H>
+static hipError_t jacobi9_pass(int nx, int ny, double inv_diag, double off,
+                               const double *b, const double *xin,
+                               double *xout, hipStream_t s)
+{
+    constexpr int W = J9_TS + 2 * H;
+    const size_t lds = sizeof(double) * 3 * W * W;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(
+            (const void *)jacobi9_tb_kernel<H>,
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    dim3 grid((nx + J9_TS - 1) / J9_TS, (ny + J9_TS - 1) / J9_TS);
+    hipLaunchKernelGGL(jacobi9_tb_kernel<H>, grid, dim3(J9_NT), lds, s, nx,
+                       ny, inv_diag, off, b, xin, xout);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi9(int nx, int ny, double diag, double off,
+                          const double *b, double *x, double *tmp, int iters,
+                          int tblock, hipStream_t s)
+{
+    const double inv_diag = 1.0 / diag;
+    double *cur = x, *nxt = tmp;
+    int left = iters;
+    while (left > 0) {
+        // passes of tblock iterations, the remainder in powers of two
+        int h = tblock;
+        while (h > left) h >>= 1;
+        hipError_t e;
+        switch (h) {
+        case 8: e = jacobi9_pass<8>(nx, ny, inv_diag, off, b, cur, nxt, s); break;
+        case 4: e = jacobi9_pass<4>(nx, ny, inv_diag, off, b, cur, nxt, s); break;
+        case 2: e = jacobi9_pass<2>(nx, ny, inv_diag, off, b, cur, nxt, s); break;
+        default: e = jacobi9_pass<1>(nx, ny, inv_diag, off, b, cur, nxt, s); break;
+        }
+        if (e != hipSuccess) return e;
+        std::swap(cur, nxt);
+        left -= h;
+    }
+    if (cur != x)
+        return hipMemcpyAsync(x, cur, sizeof(double) * (size_t)nx * ny,
+                              hipMemcpyDeviceToDevice, s);
+    return hipSuccess;
+}
+
+}  // namespace m2s

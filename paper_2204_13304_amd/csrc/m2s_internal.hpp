@@ -306,6 +306,12 @@ hipError_t launch_sweep7v(const m2s_stencil &A, const void *r,
                           Workspace &ws, const SweepPlan &plan,
                           hipStream_t s);
 
+// Jacobi iterations of the 2-D 9-point operator, temporally blocked
+// (k_jacobi.hip); the result ends in x, tmp is a second nx*ny buffer.
+hipError_t launch_jacobi9(int nx, int ny, double diag, double off,
+                          const double *b, double *x, double *tmp, int iters,
+                          int tblock, hipStream_t s);
+
 // bytes of one boundary record: the value and the launch epoch
 inline size_t c27_record_bytes(m2s_dtype t) { return t == M2S_F64 ? 16 : 8; }
 
