@@ -90,8 +90,9 @@ def parse():
                     help="skip the block SSOR and VAR7 workloads")
     ap.add_argument("--workloads-only", action="store_true",
                     help="only the block SSOR and VAR7 workloads")
-    ap.add_argument("--workloads", default="ssor,var7,jacobi",
-                    help="which of them: ssor, var7, jacobi (comma-separated)")
+    ap.add_argument("--workloads", default="ssor,var7,jacobi,penta",
+                    help="which of them: ssor, var7, jacobi, penta "
+                         "(comma-separated)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the kernel loops and a copy calibration")
     return ap.parse_args()
@@ -117,7 +118,7 @@ def flops_per_iteration(n, levels):
 
 
 def extra_workloads(torch, m, inputs, dev, reps,
-                    which=("ssor", "var7", "jacobi")):
+                    which=("ssor", "var7", "jacobi", "penta")):
     """Block SSOR (162^3 x 5) and the VAR7 solve with its gradient (128^3)."""
     out = {}
     if "ssor" in which:
@@ -126,7 +127,36 @@ def extra_workloads(torch, m, inputs, dev, reps,
         out.update(var7_workload(torch, m, inputs, dev, reps))
     if "jacobi" in which:
         out.update(jacobi_workload(torch, m, inputs, dev, reps))
+    if "penta" in which:
+        out.update(penta_workload(torch, m, inputs, dev, reps))
     return out
+
+
+def penta_workload(torch, m, inputs, dev, reps):
+    """Pentadiagonal line solves along x, y and z at 162^3 (SP-shaped,
+    synthetic diagonally dominant coefficients)."""
+    n = 162
+    shape = (n, n, n)
+    coef = torch.from_numpy(inputs.uniform(42, (5,) + shape)).to(dev)
+    coef[2] += 6.0
+    r = torch.from_numpy(inputs.standard_normal(43, shape)).to(dev)
+    x = torch.empty_like(r)
+    work = torch.empty((2,) + shape, dtype=torch.float64, device=dev)
+    res = {}
+    for axis in ("x", "y", "z"):
+        m.penta_lines(coef, r, axis, x, work)
+        res[axis] = event_ms(
+            torch, lambda: m.penta_lines(coef, r, axis, x, work), reps)
+    gbs = {a: 104 * n ** 3 / (t * 1e-3) / 1e9 for a, t in res.items()}
+    log("penta lines 162^3: " + ", ".join(
+        f"{a} {res[a]:.3f} ms ({gbs[a]:.0f} GB/s)" for a in res))
+    return {"penta_lines": {
+        "workload": "pentadiagonal systems along every x, y, z line of "
+                    "162^3, FP64, bands U(-1,1) (+6 on the diagonal) seed 42",
+        "ms": res, "achieved": gbs,
+        "unit": "GB/s (104 B per point: read 5 bands and r, write and "
+                "reread the normalised row, write x)",
+        "frac": {a: g / HBM_PEAK_GBS for a, g in gbs.items()}}}
 
 
 def jacobi_workload(torch, m, inputs, dev, reps):

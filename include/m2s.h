@@ -297,6 +297,23 @@ m2s_status m2s_jacobi9(int32_t nx, int32_t ny, double diag, double off,
                        int32_t tblock, hipStream_t stream);
 
 /* ---------------------------------------------------------------------
+ * Pentadiagonal line solves (the scalar multi-diagonal systems of the
+ * ADI-shaped NPB SP solver, Sec. 7.1): along axis 0 (x), 1 (y) or 2 (z)
+ * every grid line of an nx x ny x nz grid ([nz][ny][nx], F64) holds
+ *   a_i x_{i-2} + b_i x_{i-1} + c_i x_i + d_i x_{i+1} + e_i x_{i+2} = r_i
+ * (i the position on the line; terms reaching off the line are ignored).
+ * coef: 5 consecutive fields a, b, c, d, e (5 n doubles); r: n doubles;
+ * x: the solution (n doubles, overwritten); work: 2 n doubles of caller-
+ * owned scratch (overwritten).  Gaussian elimination without pivoting
+ * (the systems must be safe for it, e.g. diagonally dominant), one line per
+ * GPU thread, elimination and back substitution in one launch.  None of the
+ * four buffers may overlap; n < 2^31.
+ * --------------------------------------------------------------------- */
+m2s_status m2s_penta_lines(int32_t nx, int32_t ny, int32_t nz, int32_t axis,
+                           const double *coef, const double *r, double *x,
+                           double *work, hipStream_t stream);
+
+/* ---------------------------------------------------------------------
  * Schedule of the wavefront sweep (host only, no GPU needed), exposed so
  * the schedule's legality (every dependence from a strictly earlier step)
  * can be checked on the CPU.  Point (i, j, k) runs at step

@@ -85,6 +85,8 @@ _SIGS = {
     "m2s_face_grad": (C.c_int, [_S, _P, _P, _P, _P, _P, _P]),
     "m2s_jacobi9": (C.c_int, [C.c_int32, C.c_int32, C.c_double, C.c_double,
                               _P, _P, _P, C.c_int32, C.c_int32, _P]),
+    "m2s_penta_lines": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                  _P, _P, _P, _P, _P]),
     "m2s_dot": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
     "m2s_convert": (C.c_int, [_P, C.c_int, _P, C.c_int, C.c_int64, _P]),
     "m2s_plan_sweep": (C.c_int, [_S, C.POINTER(SweepPlanC)]),

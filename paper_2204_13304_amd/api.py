@@ -311,6 +311,28 @@ def jacobi9(b, x, iters, tblock=8, diag=8.0, off=-1.0, tmp=None):
     return x
 
 
+def penta_lines(coef, r, axis, x=None, work=None):
+    """Solve the pentadiagonal systems along every grid line of `axis`
+    ("x", "y" or "z"); coef (5, nz, ny, nx) holds the bands a..e."""
+    lib = L.load()
+    if r.dim() != 3:
+        raise ValueError("penta_lines takes 3-D fields (nz, ny, nx)")
+    nz, ny, nx = r.shape
+    _need(r, torch.float64, (nz, ny, nx), "r")
+    _need(coef, torch.float64, (5, nz, ny, nx), "coef")
+    if x is None:
+        x = torch.empty_like(r)
+    if work is None:
+        work = torch.empty((2, nz, ny, nx), dtype=torch.float64,
+                           device=r.device)
+    _need(x, torch.float64, (nz, ny, nx), "x")
+    _need(work, torch.float64, (2, nz, ny, nx), "work")
+    L.check(lib.m2s_penta_lines(nx, ny, nz, {"x": 0, "y": 1, "z": 2}[axis],
+                                _ptr(coef), _ptr(r), _ptr(x), _ptr(work),
+                                _stream()), "m2s_penta_lines")
+    return x
+
+
 def face_grad(A: Stencil, u, lam):
     lib = L.load()
     nz, ny, nx = A.shape

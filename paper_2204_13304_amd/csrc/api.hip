@@ -135,6 +135,14 @@ bool overlap(const void *a, const void *b, size_t bytes)
     return x < y + bytes && y < x + bytes;
 }
 
+// [a, a + na) and [b, b + nb) share a byte
+bool overlap2(const void *a, size_t na, const void *b, size_t nb)
+{
+    if (!a || !b) return false;
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + nb && y < x + na;
+}
+
 m2s_status hip_status(hipError_t e)
 {
     return e == hipSuccess ? M2S_OK : M2S_ERR_HIP;
@@ -625,6 +633,23 @@ m2s_status m2s_ssor_sweep_sequential(const m2s_stencil *A, const void *b,
     if (dir & M2S_BWD)
         M2S_TRY(launch_sweep_sequential_b7(*A, C, omega, b, x, true, stream));
     return M2S_OK;
+}
+
+m2s_status m2s_penta_lines(int32_t nx, int32_t ny, int32_t nz, int32_t axis,
+                           const double *coef, const double *r, double *x,
+                           double *work, hipStream_t stream)
+{
+    if (!coef || !r || !x || !work || axis < 0 || axis > 2) return M2S_ERR_ARG;
+    if (nx < 1 || ny < 1 || nz < 1 ||
+        (int64_t)nx * ny * nz >= ((int64_t)1 << 31))
+        return M2S_ERR_SHAPE;
+    const size_t vb = sizeof(double) * (size_t)nx * ny * nz;
+    if (overlap2(coef, 5 * vb, r, vb) || overlap2(coef, 5 * vb, x, vb) ||
+        overlap2(coef, 5 * vb, work, 2 * vb) || overlap(r, x, vb) ||
+        overlap2(r, vb, work, 2 * vb) || overlap2(x, vb, work, 2 * vb))
+        return M2S_ERR_ALIAS;
+    return hip_status(
+        launch_penta_lines(nx, ny, nz, axis, coef, r, x, work, stream));
 }
 
 m2s_status m2s_jacobi9(int32_t nx, int32_t ny, double diag, double off,

@@ -312,6 +312,11 @@ hipError_t launch_jacobi9(int nx, int ny, double diag, double off,
                           const double *b, double *x, double *tmp, int iters,
                           int tblock, hipStream_t s);
 
+// Pentadiagonal line solves along one axis (k_lines.hip); work: 2n doubles.
+hipError_t launch_penta_lines(int nx, int ny, int nz, int axis,
+                              const double *coef, const double *r, double *x,
+                              double *work, hipStream_t s);
+
 // bytes of one boundary record: the value and the launch epoch
 inline size_t c27_record_bytes(m2s_dtype t) { return t == M2S_F64 ? 16 : 8; }
 

@@ -1,5 +1,6 @@
-"""GPU parity of the microbenchmark kernels (Sec. 7.2.1): Jacobi iterations
-of the 2-D 9-point operator, temporally blocked, against the oracle."""
+"""GPU parity of the microbenchmark kernels (Sec. 7.2.1: Jacobi iterations
+of the 2-D 9-point operator, temporally blocked) and of the pentadiagonal
+line solves (Sec. 7.1, SP-shaped), against the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -64,3 +65,38 @@ def test_jacobi9_rejects_bad_arguments(m):
         m.jacobi9(b, x, 3, tblock=3)
     with pytest.raises(RuntimeError):
         m.jacobi9(b, x, 3, tmp=x)
+
+
+def _penta(shape, seed):
+    rng = np.random.default_rng(seed)
+    coef = rng.uniform(-1.0, 1.0, (5,) + shape)
+    coef[2] += 6.0
+    return coef, rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("axis", ["x", "y", "z"])
+@pytest.mark.parametrize("shape", [(7, 9, 11), (1, 1, 1), (3, 65, 2),
+                                   (33, 4, 70)])
+def test_penta_lines_parity(m, axis, shape):
+    banner(f"penta {axis} {shape}")
+    coef, r = _penta(shape, 40)
+    x = m.penta_lines(dev(coef), dev(r), axis)
+    ref = oracle.penta_lines(coef, r, axis)
+    assert rel_inf(host(x), ref) <= 1e-13
+
+
+def test_penta_lines_full_size_162(m):
+    shape = (162, 162, 162)
+    banner("penta 162^3")
+    coef, r = _penta(shape, 41)
+    cg, rg = dev(coef), dev(r)
+    for axis in ("x", "y", "z"):
+        x = m.penta_lines(cg, rg, axis)
+        assert rel_inf(host(x), oracle.penta_lines(coef, r, axis)) <= 1e-13
+
+
+def test_penta_lines_rejects_aliasing(m):
+    coef = torch.zeros((5, 4, 4, 4), dtype=torch.float64, device="cuda")
+    r = torch.zeros((4, 4, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(RuntimeError):
+        m.penta_lines(coef, r, "x", x=coef[0])
