@@ -90,8 +90,8 @@ def parse():
                     help="skip the block SSOR and VAR7 workloads")
     ap.add_argument("--workloads-only", action="store_true",
                     help="only the block SSOR and VAR7 workloads")
-    ap.add_argument("--workloads", default="ssor,var7,jacobi,penta",
-                    help="which of them: ssor, var7, jacobi, penta "
+    ap.add_argument("--workloads", default="ssor,var7,jacobi,penta,ilu",
+                    help="which of them: ssor, var7, jacobi, penta, ilu "
                          "(comma-separated)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the kernel loops and a copy calibration")
@@ -118,7 +118,7 @@ def flops_per_iteration(n, levels):
 
 
 def extra_workloads(torch, m, inputs, dev, reps,
-                    which=("ssor", "var7", "jacobi", "penta")):
+                    which=("ssor", "var7", "jacobi", "penta", "ilu")):
     """Block SSOR (162^3 x 5) and the VAR7 solve with its gradient (128^3)."""
     out = {}
     if "ssor" in which:
@@ -129,7 +129,36 @@ def extra_workloads(torch, m, inputs, dev, reps,
         out.update(jacobi_workload(torch, m, inputs, dev, reps))
     if "penta" in which:
         out.update(penta_workload(torch, m, inputs, dev, reps))
+    if "ilu" in which:
+        out.update(ilu_workload(torch, m, inputs, dev, reps))
     return out
+
+
+def ilu_workload(torch, m, inputs, dev, reps):
+    """ILU of the 27-point operator at 256^3 (Sec. 7.2.1 microbenchmark at
+    the sweep's size): the factor sweep and one application M^-1 r (a lower
+    and an upper triangular sweep)."""
+    n = 256
+    shape = (n, n, n)
+    A = m.const27(shape)
+    ws = m.Workspace(A)
+    r = torch.from_numpy(inputs.standard_normal(52, shape)).to(dev)
+    w = m.ilu27_factor(A, ws)
+    z = torch.empty_like(r)
+    m.ilu27_apply(A, w, r, z, ws)
+    tf = event_ms(torch, lambda: m.ilu27_factor(A, ws), reps)
+    ta = event_ms(torch, lambda: m.ilu27_apply(A, w, r, z, ws), reps)
+    ws.check()
+    gbs = 48 * n ** 3 / (ta * 1e-3) / 1e9
+    log(f"ilu27 256^3: factor {tf:.3f} ms, apply {ta:.3f} ms "
+        f"({gbs:.0f} GB/s)")
+    return {"ilu27": {
+        "workload": "ILU (factored diagonal) of the 27-point 26/-1 "
+                    "operator at 256^3, FP64, r ~ N(0,1) seed 52",
+        "factor_ms": tf, "apply_ms": ta, "apply_achieved": gbs,
+        "unit": "GB/s (apply: 48 B per point -- read r, w, write y; "
+                "read y, w, write z)",
+        "apply_frac": gbs / HBM_PEAK_GBS}}
 
 
 def penta_workload(torch, m, inputs, dev, reps):

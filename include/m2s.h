@@ -281,6 +281,26 @@ m2s_status m2s_convert(const void *src, m2s_dtype src_t, void *dst,
                        m2s_dtype dst_t, int64_t n, hipStream_t stream);
 
 /* ---------------------------------------------------------------------
+ * ILU of the 27-point operator (the ILU microbenchmark of Sec. 7.2.1),
+ * CONST27 F64: M = (D + L) D^{-1} (D + U) with L, U the strict lower and
+ * upper parts of A and the diagonal D = diag(d) factored so that
+ * diag(M) = diag(A):  d_p = diag - sum_{q lower} off^2 / d_q.
+ * m2s_ilu27_factor writes w = 1/d (n doubles, caller-owned).
+ * m2s_ilu27_apply computes z = M^{-1} r: the lower solve
+ *   y_p = (r_p - off sum_{q lower} y_q) / d_p,  p ascending,
+ * into the workspace's scratch vector, then the upper solve
+ *   z_p = y_p - off (sum_{q upper} z_q) / d_p,  p descending.
+ * All three are exact lexicographic sweeps over the 13 lower neighbours in
+ * sweep order, run on the 27-point wavefront tiles (1 or 2 compute
+ * wavefronts per tile, M2S_ERR_HIP otherwise).  r, w, z must not overlap.
+ * --------------------------------------------------------------------- */
+m2s_status m2s_ilu27_factor(const m2s_stencil *A, void *w, m2s_workspace *ws,
+                            hipStream_t stream);
+m2s_status m2s_ilu27_apply(const m2s_stencil *A, const void *w,
+                           const void *r, void *z, m2s_workspace *ws,
+                           hipStream_t stream);
+
+/* ---------------------------------------------------------------------
  * Jacobi iterations of the 2-D 9-point operator (the JacIter
  * microbenchmark of Sec. 7.2.1): on an nx x ny grid ([ny][nx], x fastest,
  * F64), iters times

@@ -311,6 +311,30 @@ def jacobi9(b, x, iters, tblock=8, diag=8.0, off=-1.0, tmp=None):
     return x
 
 
+def ilu27_factor(A: Stencil, ws: Workspace | None = None):
+    """w = 1/d, the factor of the 27-point ILU M = (D+L) D^-1 (D+U)."""
+    lib = L.load()
+    w = torch.empty(A.field_shape, dtype=A.dtype, device="cuda")
+    ws = ws or Workspace(A)
+    L.check(lib.m2s_ilu27_factor(A.ref(), _ptr(w), ws.handle, _stream()),
+            "m2s_ilu27_factor")
+    return w
+
+
+def ilu27_apply(A: Stencil, w, r, z=None, ws: Workspace | None = None):
+    """z = M^-1 r (lower, then upper triangular sweep)."""
+    lib = L.load()
+    _need(w, A.dtype, A.field_shape, "w")
+    _need(r, A.dtype, A.field_shape, "r")
+    if z is None:
+        z = torch.empty_like(r)
+    _need(z, A.dtype, A.field_shape, "z")
+    ws = ws or Workspace(A)
+    L.check(lib.m2s_ilu27_apply(A.ref(), _ptr(w), _ptr(r), _ptr(z),
+                                ws.handle, _stream()), "m2s_ilu27_apply")
+    return z
+
+
 def penta_lines(coef, r, axis, x=None, work=None):
     """Solve the pentadiagonal systems along every grid line of `axis`
     ("x", "y" or "z"); coef (5, nz, ny, nx) holds the bands a..e."""

@@ -635,6 +635,45 @@ m2s_status m2s_ssor_sweep_sequential(const m2s_stencil *A, const void *b,
     return M2S_OK;
 }
 
+namespace {
+m2s_status ilu27_prepare(const m2s_stencil *A, m2s_workspace *ws,
+                         SweepPlan &P)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (A->kind != M2S_CONST27) return M2S_ERR_UNSUPPORTED;
+    if (A->dtype != M2S_F64) return M2S_ERR_DTYPE;
+    if ((st = check_ws(*A, ws)) != M2S_OK) return st;
+    if ((st = make_plan(*A, P, true)) != M2S_OK) return st;
+    return ensure_tiles(ws, P.slab_planes / 4);
+}
+}  // namespace
+
+m2s_status m2s_ilu27_factor(const m2s_stencil *A, void *w, m2s_workspace *ws,
+                            hipStream_t stream)
+{
+    if (!w) return M2S_ERR_ARG;
+    SweepPlan P{};
+    m2s_status st = ilu27_prepare(A, ws, P);
+    if (st != M2S_OK) return st;
+    return hip_status(launch_ilu27(*A, 1, nullptr, nullptr, w, *ws, P, stream));
+}
+
+m2s_status m2s_ilu27_apply(const m2s_stencil *A, const void *w,
+                           const void *r, void *z, m2s_workspace *ws,
+                           hipStream_t stream)
+{
+    if (!w || !r || !z) return M2S_ERR_ARG;
+    SweepPlan P{};
+    m2s_status st = ilu27_prepare(A, ws, P);
+    if (st != M2S_OK) return st;
+    const size_t vb = (size_t)npoints(*A) * elem_size(*A);
+    if (overlap(w, r, vb) || overlap(w, z, vb) || overlap(r, z, vb))
+        return M2S_ERR_ALIAS;
+    M2S_TRY(launch_ilu27(*A, 2, r, w, ws->scratch, *ws, P, stream));
+    return hip_status(launch_ilu27(*A, 3, ws->scratch, w, z, *ws, P, stream));
+}
+
 m2s_status m2s_penta_lines(int32_t nx, int32_t ny, int32_t nz, int32_t axis,
                            const double *coef, const double *r, double *x,
                            double *work, hipStream_t stream)

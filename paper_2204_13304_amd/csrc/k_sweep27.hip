@@ -81,6 +81,10 @@ struct C27Args {
     const T *xin;        // nullptr: start from zero
     T *xout;
     T off, inv_diag;
+    // ILU modes (see the kernel): per-point weight w = 1 / d, and the
+    // constant diagonal of the factor sweep
+    const T *w;
+    T diagc;
     void *bnd;           // boundary store (records)
     int64_t bnd_elems;   // records
     unsigned epoch;      // this launch's tag, never 0
@@ -105,7 +109,13 @@ __host__ __device__ inline int c27_slot(int ut, int vt, int KT, int nutb)
 // its own step loop with the same number of barriers, so every wavefront
 // waits only for its own memory instructions.  A value written in step T by
 // one wavefront is first read in step T + 1 by another.
-template <typename T, bool BWD, bool ZERO, int NW>
+// MODE selects what a point computes from S, the sum over its 13 lower
+// neighbours in sweep order (ZERO: the upper ones are 0 then):
+//   0  SymGS      x = (r - off (S + upper)) / diag
+//   1  ILU factor w = 1 / (diagc - off S)        (off = off^2, x is w)
+//   2  ILU lower  y = (r - off S) w
+//   3  ILU upper  z = r - off S w                (backward sweep, r = y)
+template <typename T, bool BWD, bool ZERO, int NW, int MODE>
 __global__ void __launch_bounds__(64 * (2 * NW + 1))
     c27_tile_kernel(C27Args<T> a)
 {
@@ -119,6 +129,7 @@ __global__ void __launch_bounds__(64 * (2 * NW + 1))
     extern __shared__ unsigned char smem_raw[];
     T *const xr = (T *)smem_raw;
     T *const rr = xr + NRING * C27_WP;
+    T *const wr = rr + KT * C27_TU * C27_WRP;  // ILU modes 2, 3
     __shared__ int s_tile, s_abort;
 
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
@@ -139,6 +150,9 @@ __global__ void __launch_bounds__(64 * (2 * NW + 1))
     };
     auto rrow = [&](int kq, int uq) -> T * {
         return rr + (kq * C27_TU + uq) * C27_WRP;
+    };
+    auto wrow = [&](int kq, int uq) -> T * {
+        return wr + (kq * C27_TU + uq) * C27_WRP;
     };
     // element index of virtual column 0 of row (j, k); dir steps along it
     auto rowbase = [&](int j, int k) -> int {
@@ -185,6 +199,7 @@ __global__ void __launch_bounds__(64 * (2 * NW + 1))
             const int sc = 2 * (uc + kc);
             T *const own = xrow(kk, cl);
             T *const rown = rrow(kk, cl);
+            T *const wown = wrow(kk, cl);
             // boundary rows: u0 + 14, u0 + 15 of every plane (entries 0 ..
             // 2KT - 1) and u0 .. u0 + 13 of the top plane (2KT .. 2KT + 13)
             const int ipub = cl >= 14 ? (cl - 14) + 2 * kk
@@ -214,9 +229,20 @@ __global__ void __launch_bounds__(64 * (2 * NW + 1))
                     const T v6 = own[c2 + PS + RW];
                     const T v7 = own[c2 + PS + 2 * RW];
                     const T xo2 = own[c2];
-                    const T rf = rown[f & (C27_WR - 1)];
+                    const T rf = MODE == 1 ? a.diagc : rown[f & (C27_WR - 1)];
                     const T D = v2 + v3;
-                    const T x = c27_combine(rf, Bn, D, xprev, off, inv_diag);
+                    T x;
+                    if constexpr (MODE == 0) {
+                        x = c27_combine(rf, Bn, D, xprev, off, inv_diag);
+                    } else if constexpr (MODE == 1) {
+                        x = T(1) / c27_combine(rf, Bn, D, xprev, off, T(1));
+                    } else if constexpr (MODE == 2) {
+                        x = c27_combine(rf, Bn, D, xprev, off,
+                                        wown[f & (C27_WR - 1)]);
+                    } else {
+                        const T t = c27_combine(zero, Bn, D, xprev, off, T(1));
+                        x = fma(t, wown[f & (C27_WR - 1)], rf);
+                    }
                     const bool act = vc && (unsigned)f < (unsigned)nx;
                     if (act) {
                         own[f & (C27_W - 1)] = x;
@@ -248,13 +274,18 @@ __global__ void __launch_bounds__(64 * (2 * NW + 1))
             const __amdgpu_buffer_rsrc_t rs_o =
                 __builtin_amdgcn_make_buffer_rsrc((void *)a.xout, 0, nbytes,
                                                   0x00020000);
+            const __amdgpu_buffer_rsrc_t rs_w =
+                __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)(MODE >= 2 ? a.w : a.xout), 0,
+                    MODE >= 2 ? nbytes : 0, 0x00020000);
             // Rows of step T: rho = 8 (T mod 8) + lane / 8, column lane % 8;
             // each row gets an 8-column window of x_old ([f + 9, f + 17)),
             // of r ([f + 1, f + 9)) and stores its finished [f - 8, f)
             // every 8 steps; loads are parked 8 steps in registers.
-            T xpipe[8], rpipe[8], hpipe[8];
+            T xpipe[8], rpipe[8], hpipe[8], wpipe[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) xpipe[q] = rpipe[q] = hpipe[q] = zero;
+            for (int q = 0; q < 8; ++q)
+                xpipe[q] = rpipe[q] = hpipe[q] = wpipe[q] = zero;
             const int q8 = l & 7, r8 = l >> 3;
             for (int blk = 0; blk < nblk; ++blk) {
                 const int Tb = T_start + 16 * blk;
@@ -274,10 +305,15 @@ __global__ void __launch_bounds__(64 * (2 * NW + 1))
                                   cs = f - 8 + q8;
                         xw[cx & (C27_W - 1)] = xpipe[p8];
                         rrow(kL, uL)[cr & (C27_WR - 1)] = rpipe[p8];
+                        if constexpr (MODE >= 2)
+                            wrow(kL, uL)[cr & (C27_WR - 1)] = wpipe[p8];
                         const T xv = xw[cs & (C27_W - 1)];
                         if (!ZERO)
                             xpipe[p8] = buf_load<T>(rs_x, boff(v, rb, cx + 8));
-                        rpipe[p8] = buf_load<T>(rs_r, boff(v, rb, cr + 8));
+                        if constexpr (MODE != 1)
+                            rpipe[p8] = buf_load<T>(rs_r, boff(v, rb, cr + 8));
+                        if constexpr (MODE >= 2)
+                            wpipe[p8] = buf_load<T>(rs_w, boff(v, rb, cr + 8));
                         buf_store<T, 0>(rs_o, boff(v, rb, cs), xv);
                     }
                     // -- old-value halo rows: u0 + 16, u0 + 17 of this
@@ -412,20 +448,20 @@ C27Layout c27_layout(Grid g, int nw)
 
 int c27_threads(int nw) { return 64 * (2 * nw + 1); }
 
-size_t c27_lds_bytes(int nw, m2s_dtype t)
+size_t c27_lds_bytes(int nw, m2s_dtype t, int mode)
 {
     const int kt = 4 * nw;
     const size_t es = t == M2S_F64 ? 8 : 4;
     return ((size_t)(kt + 2) * C27_RU * C27_WP +
-            (size_t)kt * C27_TU * C27_WRP) *
+            (size_t)(mode >= 2 ? 2 : 1) * kt * C27_TU * C27_WRP) *
            es;
 }
 
-template <typename T, bool BWD, bool ZERO, int NW>
+template <typename T, bool BWD, bool ZERO, int NW, int MODE = 0>
 static hipError_t c27_launch_t(const C27Args<T> &a, int grid, size_t lds,
                                hipStream_t s)
 {
-    auto k = c27_tile_kernel<T, BWD, ZERO, NW>;
+    auto k = c27_tile_kernel<T, BWD, ZERO, NW, MODE>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(
@@ -461,12 +497,70 @@ static hipError_t c27_launch_dir(const C27Args<T> &a, bool bwd, bool zero,
                 : c27_launch_nw<T, false, false>(a, nw, grid, lds, s);
 }
 
+template <int MODE, bool BWD>
+static hipError_t c27_launch_ilu(const C27Args<double> &a, int nw, int grid,
+                                 size_t lds, hipStream_t s)
+{
+    // 4 compute wavefronts would need more LDS than a CU has with the
+    // weight ring
+    switch (nw) {
+    case 1: return c27_launch_t<double, BWD, true, 1, MODE>(a, grid, lds, s);
+    case 2: return c27_launch_t<double, BWD, true, 2, MODE>(a, grid, lds, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_ilu27(const m2s_stencil &A, int mode, const void *r,
+                        const void *w, void *out, Workspace &ws,
+                        const SweepPlan &plan, hipStream_t s)
+{
+    const int nw = plan.slab_planes / 4;
+    // reject before the workspace's ticket base and epoch move
+    if (A.dtype != M2S_F64 || (nw != 1 && nw != 2) || mode < 1 || mode > 3)
+        return hipErrorInvalidValue;
+    const size_t lds = c27_lds_bytes(nw, A.dtype, mode);
+    const uint64_t base = ws.ticket_base;
+    ws.ticket_base += (uint64_t)plan.nslabs + (uint64_t)plan.grid;
+    if (++ws.epoch == 0) ++ws.epoch;
+    C27Args<double> a{};
+    a.g = Grid{A.ext.nx, A.ext.ny, A.ext.nz};
+    a.ntiles = plan.nslabs;
+    a.nutb = ws.tile_nutb;
+    a.ns = ws.tile_ns;
+    a.tiles = ws.tile_list;
+    a.ticket = ws.ticket;
+    a.ticket_base = base;
+    a.err = ws.err;
+    const char *e = getenv("M2S_SPIN_LIMIT");
+    a.spin_limit = e ? std::max(1, atoi(e)) : (1 << 22);
+    a.r = (const double *)(r ? r : out);
+    a.xin = nullptr;
+    a.xout = (double *)out;
+    a.w = (const double *)w;
+    a.bnd = ws.bnd;
+    a.bnd_elems = ws.bnd_elems;
+    a.epoch = ws.epoch;
+    switch (mode) {
+    case 1:  // factor: w = 1 / (diag - off^2 S), forward
+        a.off = A.offdiag * A.offdiag;
+        a.diagc = A.diag;
+        return c27_launch_ilu<1, false>(a, nw, plan.grid, lds, s);
+    case 2:  // lower solve, forward
+        a.off = A.offdiag;
+        return c27_launch_ilu<2, false>(a, nw, plan.grid, lds, s);
+    case 3:  // upper solve, backward
+        a.off = A.offdiag;
+        return c27_launch_ilu<3, true>(a, nw, plan.grid, lds, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_sweep27(const m2s_stencil &A, const void *r,
                           const void *xin, void *xout, bool bwd,
                           Workspace &ws, const SweepPlan &plan, hipStream_t s)
 {
     const int nw = plan.slab_planes / 4;
-    const size_t lds = c27_lds_bytes(nw, A.dtype);
+    const size_t lds = c27_lds_bytes(nw, A.dtype, 0);
     // this launch takes tickets [base, base + ntiles + grid)
     const uint64_t base = ws.ticket_base;
     ws.ticket_base += (uint64_t)plan.nslabs + (uint64_t)plan.grid;

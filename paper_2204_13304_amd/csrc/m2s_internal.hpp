@@ -280,7 +280,13 @@ struct C27Layout {
     std::vector<int2> tiles;  // valid tiles in ticket order
 };
 C27Layout c27_layout(Grid g, int nw);
-size_t c27_lds_bytes(int nw, m2s_dtype t);
+size_t c27_lds_bytes(int nw, m2s_dtype t, int mode);
+// ILU of the 27-point operator on the same tiles (F64): mode 1 factor
+// (out = w = 1/d), 2 lower solve (out = y from r), 3 upper solve (out = z
+// from r = y); w is the factor's weight array for modes 2 and 3.
+hipError_t launch_ilu27(const m2s_stencil &A, int mode, const void *r,
+                        const void *w, void *out, Workspace &ws,
+                        const SweepPlan &plan, hipStream_t s);
 int c27_threads(int nw);  // nw compute + nw memory + 1 poll wavefronts
 // Tiling of the block SSOR sweep: rectangular tiles of 16 j by 4 * nw k.
 struct B7Layout {

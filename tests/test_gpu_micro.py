@@ -100,3 +100,50 @@ def test_penta_lines_rejects_aliasing(m):
     r = torch.zeros((4, 4, 4), dtype=torch.float64, device="cuda")
     with pytest.raises(RuntimeError):
         m.penta_lines(coef, r, "x", x=coef[0])
+
+
+@pytest.mark.parametrize("shape", [(9, 7, 6), (16, 16, 16), (13, 26, 9),
+                                   (33, 20, 17), (1, 1, 5)])
+@pytest.mark.parametrize("nw", ["1", "2"])
+def test_ilu27_factor_and_apply(m, shape, nw, monkeypatch):
+    banner(f"ilu27 {shape} nw {nw}")
+    monkeypatch.setenv("M2S_C27_WAVES", nw)
+    A = m.const27(shape)
+    ws = m.Workspace(A)
+    w = m.ilu27_factor(A, ws)
+    d = oracle.ilu27_factor(shape)
+    assert rel_inf(host(w), 1.0 / d) <= 1e-13
+    r = inputs.standard_normal(50, shape)
+    z = m.ilu27_apply(A, w, dev(r), ws=ws)
+    assert rel_inf(host(z), oracle.ilu27_solve(d, r)) <= 1e-13
+
+
+def test_ilu27_full_size_256(m):
+    shape = (256, 256, 256)
+    banner("ilu27 256^3")
+    A = m.const27(shape)
+    ws = m.Workspace(A)
+    w = m.ilu27_factor(A, ws)
+    d = oracle.ilu27_factor(shape)
+    assert rel_inf(host(w), 1.0 / d) <= 1e-13
+    r = inputs.standard_normal(51, shape)
+    z = m.ilu27_apply(A, w, dev(r), ws=ws)
+    assert rel_inf(host(z), oracle.ilu27_solve(d, r)) <= 1e-13
+
+
+def test_ilu27_rejects_tall_tiles_and_f32(m, monkeypatch):
+    monkeypatch.setenv("M2S_C27_WAVES", "4")
+    A = m.const27((8, 8, 8))
+    ws = m.Workspace(A)
+    with pytest.raises(RuntimeError):
+        m.ilu27_factor(A, ws)
+    # a rejected call leaves the workspace usable
+    r = dev(inputs.standard_normal(53, (8, 8, 8)))
+    x = dev(np.zeros((8, 8, 8)))
+    m.symgs(A, r, x, "sym", ws)
+    ref = oracle.symgs27(host(r), np.zeros((8, 8, 8)), "sym")
+    assert rel_inf(host(x), ref) <= 1e-13
+    monkeypatch.setenv("M2S_C27_WAVES", "2")
+    A32 = m.const27((8, 8, 8), dtype=torch.float32)
+    with pytest.raises(RuntimeError):
+        m.ilu27_factor(A32)
