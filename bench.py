@@ -22,17 +22,20 @@ Also reported on the same line:
   time_to_solution  FP64 MG-PCG and mixed MG-PCG (V-cycle in FP32, CG in
                     FP64) to relative residual 1e-9 from x0 = 0;
   cpu_baseline      the CPU oracle (one thread) on one MG-PCG iteration;
-  workloads         the other two workloads of the hot path:
+  workloads         the other workloads of the hot path:
                     block SSOR on the 162^3 x 5 BLOCK7 operator (20
                     iterations, omega 1.2, b = A*1, x0 = 0; 120 B per point
-                    per half-sweep) and the differentiable VAR7 solve at
+                    per half-sweep); the differentiable VAR7 solve at
                     128^3 (MG-PCG to 1e-10, then the adjoint solve and the
-                    face gradient of 0.5*|u - u_t|^2).
+                    face gradient of 0.5*|u - u_t|^2); temporally blocked
+                    Jacobi (4096^2, 64 iterations); pentadiagonal line
+                    solves (162^3, x, y, z); the 27-point ILU (256^3);
+                    the x-line scan variant of the 27-point sweep (256^3).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 2]
     python bench.py --roofline-only      (kernel loops only, for profiling)
-    python bench.py --workloads-only [--workloads ssor|var7]
-                                         (the block SSOR and VAR7 runs only)
+    python bench.py --workloads-only [--workloads ssor,var7,...]
+                                         (those workloads only)
 """
 from __future__ import annotations
 
@@ -87,12 +90,12 @@ def parse():
     ap.add_argument("--no-tts", action="store_true",
                     help="skip the time-to-solution runs")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the block SSOR and VAR7 workloads")
+                    help="skip the workloads beside the 27-point sweep")
     ap.add_argument("--workloads-only", action="store_true",
-                    help="only the block SSOR and VAR7 workloads")
-    ap.add_argument("--workloads", default="ssor,var7,jacobi,penta,ilu",
-                    help="which of them: ssor, var7, jacobi, penta, ilu "
-                         "(comma-separated)")
+                    help="only the workloads beside the 27-point sweep")
+    ap.add_argument("--workloads", default="ssor,var7,jacobi,penta,ilu,xline",
+                    help="which of them: ssor, var7, jacobi, penta, ilu, "
+                         "xline (comma-separated)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the kernel loops and a copy calibration")
     return ap.parse_args()
@@ -118,8 +121,9 @@ def flops_per_iteration(n, levels):
 
 
 def extra_workloads(torch, m, inputs, dev, reps,
-                    which=("ssor", "var7", "jacobi", "penta", "ilu")):
-    """Block SSOR (162^3 x 5) and the VAR7 solve with its gradient (128^3)."""
+                    which=("ssor", "var7", "jacobi", "penta", "ilu",
+                           "xline")):
+    """The workloads beside the 27-point sweep, by name."""
     out = {}
     if "ssor" in which:
         out.update(ssor_workload(torch, m, inputs, dev, reps))
@@ -131,7 +135,32 @@ def extra_workloads(torch, m, inputs, dev, reps,
         out.update(penta_workload(torch, m, inputs, dev, reps))
     if "ilu" in which:
         out.update(ilu_workload(torch, m, inputs, dev, reps))
+    if "xline" in which:
+        out.update(xline_workload(torch, m, inputs, dev, reps))
     return out
+
+
+def xline_workload(torch, m, inputs, dev, reps):
+    """The 27-point symmetric sweep at 256^3 scheduled by lines (step
+    j + 2k) with each x-line solved by an affine prefix scan, beside the
+    exact point-hyperplane wavefront on the same input."""
+    n = 256
+    shape = (n, n, n)
+    A = m.const27(shape)
+    ws = m.Workspace(A)
+    r = torch.from_numpy(inputs.standard_normal(10, shape)).to(dev)
+    x = torch.from_numpy(inputs.standard_normal(11, shape)).to(dev)
+    m.symgs_xline(A, r, x, "sym", ws)
+    m.symgs(A, r, x, "sym", ws)
+    tl = event_ms(torch, lambda: m.symgs_xline(A, r, x, "sym", ws), reps) / 2
+    tw = event_ms(torch, lambda: m.symgs(A, r, x, "sym", ws), reps) / 2
+    ws.check()
+    log(f"symgs27 256^3 half-sweep: x-line scan {tl:.3f} ms, "
+        f"point wavefront {tw:.3f} ms")
+    return {"symgs27_xline": {
+        "workload": "27-point 26/-1 SymGS at 256^3, FP64, lines at step "
+                    "j + 2k, x-lines by affine scan (not bitwise)",
+        "half_sweep_ms": tl, "wavefront_half_sweep_ms": tw}}
 
 
 def ilu_workload(torch, m, inputs, dev, reps):

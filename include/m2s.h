@@ -153,6 +153,21 @@ m2s_status m2s_symgs_oop(const m2s_stencil *A, const void *r,
                          const void *x_in, void *x_out, m2s_dir dir,
                          m2s_workspace *ws, hipStream_t stream);
 
+/* Line-scheduled variant of the 27-point sweep (CONST27, F64 only; an
+ * extension beyond the paper's schedules, built on the dependence
+ * structure of the Seidel-style routine of Sec. 4.3.3 / Sec. 7.2.1).  Line
+ * (j, k) is updated at step j + 2k of a line schedule; along the line the
+ * recurrence x_i = g_i - (a_off / a_pp) x_{i-1} is solved by a parallel
+ * prefix scan of affine maps.  Same update as m2s_symgs (in place, same
+ * dir values, same workspace), but the scan regroups the sums: the result
+ * equals the lexicographic sweep only up to rounding, not bitwise.
+ * Returns M2S_ERR_UNSUPPORTED for other kinds, M2S_ERR_DTYPE for F32,
+ * M2S_ERR_SHAPE when nx > 3840 (the line does not fit the scan's LDS),
+ * M2S_ERR_ALIAS if r and x overlap.  A dependency wait that times out
+ * latches M2S_ERR_TIMEOUT (read by m2s_check). */
+m2s_status m2s_symgs_xline(const m2s_stencil *A, const void *r, void *x,
+                           m2s_dir dir, m2s_workspace *ws, hipStream_t stream);
+
 /* Reference: the same sweep run by ONE GPU thread in plain lexicographic
  * order, in place.  For testing the wavefront schedule only (slow). */
 m2s_status m2s_symgs_sequential(const m2s_stencil *A, const void *r,

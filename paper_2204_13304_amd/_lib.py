@@ -71,6 +71,7 @@ _SIGS = {
     "m2s_symgs": (C.c_int, [_S, _P, _P, C.c_int, _P, _P]),
     "m2s_symgs_oop": (C.c_int, [_S, _P, _P, _P, C.c_int, _P, _P]),
     "m2s_symgs_sequential": (C.c_int, [_S, _P, _P, C.c_int, _P]),
+    "m2s_symgs_xline": (C.c_int, [_S, _P, _P, C.c_int, _P, _P]),
     "m2s_symgs_adjoint": (C.c_int, [_S, _P, _P, _P, C.c_int, _P, _P]),
     "m2s_ssor_sweep": (C.c_int, [_S, _P, _P, C.c_double, C.c_int, _P, _P]),
     "m2s_ssor_sweep_sequential": (C.c_int, [_S, _P, _P, C.c_double, C.c_int,

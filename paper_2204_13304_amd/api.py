@@ -195,6 +195,20 @@ def symgs_sequential(A: Stencil, r, x, direction="sym"):
     return x
 
 
+def symgs_xline(A: Stencil, r, x, direction="sym",
+                ws: Workspace | None = None):
+    """In-place 27-point sweep(s) on x, lines scheduled at j + 2k and each
+    x-line solved by an affine prefix scan (FP64; equal to the
+    lexicographic sweep up to rounding)."""
+    lib = L.load()
+    _need(r, A.dtype, A.field_shape, "r")
+    _need(x, A.dtype, A.field_shape, "x")
+    ws = ws or Workspace(A)
+    L.check(lib.m2s_symgs_xline(A.ref(), _ptr(r), _ptr(x), _DIRS[direction],
+                                ws.handle, _stream()), "m2s_symgs_xline")
+    return x
+
+
 def symgs_adjoint(A: Stencil, g, direction="fwd", ws: Workspace | None = None):
     """(gr, gx): gradients of <g, sweep(r, x)> w.r.t. r and x."""
     lib = L.load()

@@ -19,6 +19,12 @@ hipError_t launch_sweep_sequential_b7(const m2s_stencil &A,
                                       const Block7Consts &b7, double omega,
                                       const void *b, void *x, bool bwd,
                                       hipStream_t s);
+// k_xline.hip: line-scheduled 27-point half-sweep with the x-line scan
+// (FP64); flags holds nz 64-bit words.
+size_t xline_lds_bytes(int nx);
+hipError_t launch_xline_sweep(const m2s_stencil &A, const void *r,
+                              const void *xin, void *xout, bool bwd,
+                              Workspace &ws, uint64_t *flags, hipStream_t s);
 
 // LU with partial pivoting of the 5x5 centre block (row-major), host side.
 hipError_t fill_block7_consts(const double *blocks, Block7Consts &C)
@@ -534,6 +540,33 @@ m2s_status m2s_symgs_sequential(const m2s_stencil *A, const void *r, void *x,
     if (dir & M2S_BWD)
         M2S_TRY(launch_sweep_sequential(*A, r, x, true, stream));
     return M2S_OK;
+}
+
+m2s_status m2s_symgs_xline(const m2s_stencil *A, const void *r, void *x,
+                           m2s_dir dir, m2s_workspace *ws, hipStream_t stream)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (A->kind != M2S_CONST27) return M2S_ERR_UNSUPPORTED;
+    if (A->dtype != M2S_F64) return M2S_ERR_DTYPE;
+    if (!r || !x) return M2S_ERR_ARG;
+    if (dir != M2S_FWD && dir != M2S_BWD && dir != M2S_SYM) return M2S_ERR_ARG;
+    if ((st = check_ws(*A, ws)) != M2S_OK) return st;
+    if (xline_lds_bytes(A->ext.nx) > 64 * 1024) return M2S_ERR_SHAPE;
+    const size_t vb = (size_t)npoints(*A) * elem_size(*A);
+    if (overlap(r, x, vb)) return M2S_ERR_ALIAS;
+    // the per-plane progress words live in the second scratch vector
+    // (nz words <= the vector's nx ny nz doubles)
+    uint64_t *flags = (uint64_t *)ws->scratch2;
+    if (dir == M2S_SYM) {
+        M2S_TRY(launch_xline_sweep(*A, r, x, ws->scratch, false, *ws, flags,
+                                   stream));
+        return hip_status(launch_xline_sweep(*A, r, ws->scratch, x, true, *ws,
+                                             flags, stream));
+    }
+    M2S_TRY(launch_xline_sweep(*A, r, x, ws->scratch, dir == M2S_BWD, *ws,
+                               flags, stream));
+    return hip_status(launch_copy(x, ws->scratch, (int64_t)vb, stream));
 }
 
 m2s_status m2s_symgs_adjoint(const m2s_stencil *A, const void *g, void *gr,
