@@ -341,8 +341,9 @@ m2s_status m2s_jacobi9(int32_t nx, int32_t ny, double diag, double off,
  * x: the solution (n doubles, overwritten); work: 2 n doubles of caller-
  * owned scratch (overwritten).  Gaussian elimination without pivoting
  * (the systems must be safe for it, e.g. diagonally dominant), one line per
- * GPU thread, elimination and back substitution in one launch.  None of the
- * four buffers may overlap; n < 2^31.
+ * GPU lane (chunks of each line staged through LDS), elimination and back
+ * substitution in one launch.  None of the four buffers may overlap;
+ * n < 2^31.
  * --------------------------------------------------------------------- */
 m2s_status m2s_penta_lines(int32_t nx, int32_t ny, int32_t nz, int32_t axis,
                            const double *coef, const double *r, double *x,

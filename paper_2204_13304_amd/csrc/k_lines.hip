@@ -4,106 +4,257 @@
 // Along axis x, y or z every grid line holds the system
 //   a_i x_{i-2} + b_i x_{i-1} + c_i x_i + d_i x_{i+1} + e_i x_{i+2} = r_i.
 // Each line is a sequential (Seidel-style, 1-D) recurrence, the lines are
-// independent: one thread per line runs the forward elimination and then
-// the back substitution (fused, one launch).  The elimination keeps the
-// rows normalised -- row i becomes x_i + u_i x_{i+1} + v_i x_{i+2} = y_i --
-// so only u, v (work buffer) and y (kept in x) are stored for the way back:
+// independent: one lane per line runs the forward elimination and then the
+// back substitution (fused, one launch).  The elimination keeps the rows
+// normalised -- row i becomes x_i + u_i x_{i+1} + v_i x_{i+2} = y_i -- so
+// only u, v (work buffer) and y (kept in x) are stored for the way back:
 //   forward  reads a..e, r, writes u, v, y     (72 B per point)
 //   backward reads u, v, y, writes x           (32 B per point).
-// Threads next to each other take lines next to each other: for y and z
-// lines those are neighbouring x positions, so every access is coalesced;
-// x lines are contiguous per thread.  Loads run ahead of the recurrence
-// (the coefficients do not depend on it).
+//
+// A 64-lane workgroup takes LW = 64 / S lines and walks them in chunks of
+// 8 S points staged through LDS: the whole workgroup loads a chunk of every
+// input array with coalesced accesses (runs along x for x lines, the lines'
+// neighbouring x positions for y and z lines), lanes 0 .. LW - 1 run the
+// recurrence over their line's chunk in LDS, and the chunk's outputs leave
+// through LDS with coalesced stores.  The next chunk's loads are in flight
+// (in registers) while the current chunk is computed.  With only n^2 lines
+// the solve is bound by the loads in flight per line, not by arithmetic:
+// S lanes per line in the transfers multiply them (and the workgroups) by S
+// at the same register count per lane.
 #include "m2s_internal.hpp"
+
+#include <cstdlib>
 
 namespace m2s {
 
-constexpr int PL_NT = 64;
+constexpr int PL_NT = 64;   // lanes per workgroup
+constexpr int PL_M = 8;     // transfer elements per lane per array and chunk
 
+// LDS row stride (doubles) for S lanes per line: a pass of 16 lanes hits 16
+// distinct 8-byte banks in the x-line transfers (S = 1: 8 points of 2 lines,
+// stride 2 mod 16; S > 1: 16 points of one line, odd stride), in the y- and
+// z-line transfers and in the compute loop (consecutive lines).
+template <int S>
+constexpr int pl_ls() { return S == 1 ? 66 : PL_NT / S + 1; }
+
+template <int AXIS>
+struct LineMap {
+    int nx, ny, nz;
+    __device__ int nlines() const
+    {
+        return AXIS == 0 ? ny * nz : AXIS == 1 ? nx * nz : nx * ny;
+    }
+    __device__ int len() const { return AXIS == 0 ? nx : AXIS == 1 ? ny : nz; }
+    __device__ long stride() const
+    {
+        return AXIS == 0 ? 1 : AXIS == 1 ? (long)nx : (long)nx * ny;
+    }
+    __device__ long base(int line) const
+    {
+        if (AXIS == 0) return (long)line * nx;
+        if (AXIS == 1) {
+            const int k = line / nx, i = line - k * nx;
+            return (long)k * nx * ny + i;
+        }
+        return line;
+    }
+};
+
+// Element m of a lane's share of a chunk transfer: (line l, point q) of the
+// chunk.  x lines: consecutive lanes cover consecutive points of a line
+// (runs of 8 S values); y and z lines: consecutive lanes cover the lines.
+template <int AXIS, int S>
+__device__ __forceinline__ void chunk_elem(int t, int m, int &l, int &q)
+{
+    constexpr int LW = PL_NT / S, CHS = PL_M * S;
+    const int e = t + PL_NT * m;
+    if (AXIS == 0) {
+        l = e / CHS;
+        q = e - l * CHS;
+    } else {
+        l = e % LW;
+        q = e / LW;
+    }
+}
+
+template <int AXIS, int S>
 __global__ void __launch_bounds__(PL_NT)
-    penta_lines_kernel(int nx, int ny, int nz, int axis,
-                       const double *__restrict__ coef,
+    penta_lines_kernel(int nx, int ny, int nz, const double *__restrict__ coef,
                        const double *__restrict__ r, double *__restrict__ x,
                        double *__restrict__ work)
 {
+    constexpr int LW = PL_NT / S, CHS = PL_M * S, LS = pl_ls<S>();
+    __shared__ double sm[6][CHS * LS];
+    const LineMap<AXIS> M{nx, ny, nz};
     const long n = (long)nx * ny * nz;
-    const int line = blockIdx.x * PL_NT + threadIdx.x;
-    long base, stride;
-    int len, nlines;
-    if (axis == 0) {
-        nlines = ny * nz;
-        base = (long)line * nx;
-        stride = 1;
-        len = nx;
-    } else if (axis == 1) {
-        nlines = nx * nz;
-        const int i = line % nx, k = line / nx;
-        base = (long)k * nx * ny + i;
-        stride = nx;
-        len = ny;
-    } else {
-        nlines = nx * ny;
-        base = line;
-        stride = (long)nx * ny;
-        len = nz;
-    }
-    if (line >= nlines) return;
-    const double *ca = coef, *cb = coef + n, *cc = coef + 2 * n,
-                 *cd = coef + 3 * n, *ce = coef + 4 * n;
-    double *u = work, *v = work + n;
+    const int nl = M.nlines(), len = M.len();
+    const long st = M.stride();
+    const int t = threadIdx.x;
+    const int L0 = blockIdx.x * LW;
+    const int nch = (len + CHS - 1) / CHS;
+    const bool runs = t < LW;  // this lane runs line L0 + t
+    double *const u = work, *const v = work + n;
 
-    // forward elimination; (u1, v1, y1) row i - 1, (u2, v2, y2) row i - 2
+    // the lane's transfer elements: global base of their lines, point slots
+    long gb[PL_M];
+    int lq[PL_M], qq[PL_M];
+    bool lv[PL_M];
+#pragma unroll
+    for (int m = 0; m < PL_M; ++m) {
+        int l, q;
+        chunk_elem<AXIS, S>(t, m, l, q);
+        lv[m] = L0 + l < nl;
+        gb[m] = lv[m] ? M.base(L0 + l) : 0;
+        lq[m] = q * LS + l;
+        qq[m] = q;
+    }
+    auto gaddr = [&](int m, int c) {
+        return gb[m] + (long)(c * CHS + qq[m]) * st;
+    };
+    auto in_range = [&](int m, int c) {
+        return lv[m] && c * CHS + qq[m] < len;
+    };
+
+    // ---- forward elimination, chunks in increasing order
+    double pre[6][PL_M];
+    auto fetch_fwd = [&](int c) {
+#pragma unroll
+        for (int m = 0; m < PL_M; ++m) {
+            const bool ok = in_range(m, c);
+            const long g = ok ? gaddr(m, c) : 0;
+#pragma unroll
+            for (int a = 0; a < 5; ++a)
+                pre[a][m] = ok ? coef[a * n + g] : (a == 2 ? 1.0 : 0.0);
+            pre[5][m] = ok ? r[g] : 0.0;
+        }
+    };
     double u1 = 0, v1 = 0, y1 = 0, u2 = 0, v2 = 0, y2 = 0;
-    long p = base;
+    fetch_fwd(0);
+    for (int c = 0; c < nch; ++c) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PL_M; ++m)
+#pragma unroll
+            for (int a = 0; a < 6; ++a) sm[a][lq[m]] = pre[a][m];
+        __syncthreads();
+        if (c + 1 < nch) fetch_fwd(c + 1);
+        // the lane's own line: row q of the chunk at sm[.][q * LS + t]
+        if (runs) {
 #pragma unroll 4
-    for (int i = 0; i < len; ++i, p += stride) {
-        const double a = i >= 2 ? ca[p] : 0.0;
-        double bb = i >= 1 ? cb[p] : 0.0;
-        double c = cc[p], d = cd[p];
-        const double e = ce[p];
-        double rr = r[p];
-        // remove x_{i-2} with row i - 2, then x_{i-1} with row i - 1
-        bb -= a * u2;
-        c -= a * v2;
-        rr -= a * y2;
-        c -= bb * u1;
-        d -= bb * v1;
-        rr -= bb * y1;
-        const double inv = 1.0 / c;
-        const double ui = d * inv, vi = e * inv, yi = rr * inv;
-        u[p] = ui;
-        v[p] = vi;
-        x[p] = yi;
-        u2 = u1;
-        v2 = v1;
-        y2 = y1;
-        u1 = ui;
-        v1 = vi;
-        y1 = yi;
+            for (int q = 0; q < CHS; ++q) {
+                const int i = c * CHS + q;
+                const int o = q * LS + t;
+                const double a = i >= 2 ? sm[0][o] : 0.0;
+                double bb = i >= 1 ? sm[1][o] : 0.0;
+                double cc = sm[2][o], d = sm[3][o];
+                const double e = sm[4][o];
+                double rr = sm[5][o];
+                // remove x_{i-2} with row i - 2, then x_{i-1} with row i - 1
+                bb -= a * u2;
+                cc -= a * v2;
+                rr -= a * y2;
+                cc -= bb * u1;
+                d -= bb * v1;
+                rr -= bb * y1;
+                const double inv = 1.0 / cc;
+                const double ui = d * inv, vi = e * inv, yi = rr * inv;
+                sm[0][o] = ui;
+                sm[1][o] = vi;
+                sm[2][o] = yi;
+                u2 = u1;
+                v2 = v1;
+                y2 = y1;
+                u1 = ui;
+                v1 = vi;
+                y1 = yi;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PL_M; ++m)
+            if (in_range(m, c)) {
+                const long g = gaddr(m, c);
+                u[g] = sm[0][lq[m]];
+                v[g] = sm[1][lq[m]];
+                x[g] = sm[2][lq[m]];
+            }
     }
-    // back substitution: x_i = y_i - u_i x_{i+1} - v_i x_{i+2}
+
+    // ---- back substitution, chunks in decreasing order.  Transfers map
+    // elements to lanes the same way in both passes, so each lane loads back
+    // exactly the u, v, y values it stored itself.
+    auto fetch_bwd = [&](int c) {
+#pragma unroll
+        for (int m = 0; m < PL_M; ++m) {
+            const bool ok = in_range(m, c);
+            const long g = ok ? gaddr(m, c) : 0;
+            pre[0][m] = ok ? u[g] : 0.0;
+            pre[1][m] = ok ? v[g] : 0.0;
+            pre[2][m] = ok ? x[g] : 0.0;
+        }
+    };
     double x1 = 0, x2 = 0;
-    p = base + (long)(len - 1) * stride;
+    fetch_bwd(nch - 1);
+    for (int c = nch - 1; c >= 0; --c) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PL_M; ++m)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) sm[a][lq[m]] = pre[a][m];
+        __syncthreads();
+        if (c > 0) fetch_bwd(c - 1);
+        if (runs) {
 #pragma unroll 4
-    for (int i = len - 1; i >= 0; --i, p -= stride) {
-        const double xi = x[p] - u[p] * x1 - v[p] * x2;
-        x[p] = xi;
-        x2 = x1;
-        x1 = xi;
+            for (int q = CHS - 1; q >= 0; --q) {
+                const int i = c * CHS + q;
+                const int o = q * LS + t;
+                if (i < len) {
+                    // x_i = y_i - u_i x_{i+1} - v_i x_{i+2}
+                    const double xi =
+                        sm[2][o] - sm[0][o] * x1 - sm[1][o] * x2;
+                    sm[2][o] = xi;
+                    x2 = x1;
+                    x1 = xi;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PL_M; ++m)
+            if (in_range(m, c)) x[gaddr(m, c)] = sm[2][lq[m]];
     }
+}
+
+template <int S>
+static hipError_t penta_launch(int nx, int ny, int nz, int axis,
+                               const double *coef, const double *r,
+                               double *x, double *work, hipStream_t s)
+{
+    constexpr int LW = PL_NT / S;
+    const long nlines = axis == 0   ? (long)ny * nz
+                        : axis == 1 ? (long)nx * nz
+                                    : (long)nx * ny;
+    const int grid = (int)((nlines + LW - 1) / LW);
+    auto k = axis == 0   ? penta_lines_kernel<0, S>
+             : axis == 1 ? penta_lines_kernel<1, S>
+                         : penta_lines_kernel<2, S>;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(PL_NT), 0, s, nx, ny, nz, coef, r,
+                       x, work);
+    return hipGetLastError();
 }
 
 hipError_t launch_penta_lines(int nx, int ny, int nz, int axis,
                               const double *coef, const double *r, double *x,
                               double *work, hipStream_t s)
 {
-    const long nlines = axis == 0   ? (long)ny * nz
-                        : axis == 1 ? (long)nx * nz
-                                    : (long)nx * ny;
-    const int grid = (int)((nlines + PL_NT - 1) / PL_NT);
-    hipLaunchKernelGGL(penta_lines_kernel, dim3(grid), dim3(PL_NT), 0, s, nx,
-                       ny, nz, axis, coef, r, x, work);
-    return hipGetLastError();
+    // lanes per line in the transfers (tuning knob; 1, 2 or 4)
+    const char *e = getenv("M2S_PL_SPLIT");
+    const int split = e ? atoi(e) : 2;
+    if (split == 1)
+        return penta_launch<1>(nx, ny, nz, axis, coef, r, x, work, s);
+    if (split == 4)
+        return penta_launch<4>(nx, ny, nz, axis, coef, r, x, work, s);
+    return penta_launch<2>(nx, ny, nz, axis, coef, r, x, work, s);
 }
 
 }  // namespace m2s

@@ -85,6 +85,22 @@ def test_penta_lines_parity(m, axis, shape):
     assert rel_inf(host(x), ref) <= 1e-13
 
 
+@pytest.mark.parametrize("axis", ["x", "y", "z"])
+def test_penta_lines_split_variants_bitwise(m, axis, monkeypatch):
+    # 1, 2 or 4 lanes per line in the chunk transfers change only which
+    # lane moves which value: every variant gives the same bits
+    shape = (19, 37, 45)
+    banner(f"penta {axis} transfer splits")
+    coef, r = _penta(shape, 44)
+    outs = []
+    for split in ("1", "2", "4"):
+        monkeypatch.setenv("M2S_PL_SPLIT", split)
+        outs.append(host(m.penta_lines(dev(coef), dev(r), axis)))
+    assert rel_inf(outs[0], oracle.penta_lines(coef, r, axis)) <= 1e-13
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
 def test_penta_lines_full_size_162(m):
     shape = (162, 162, 162)
     banner("penta 162^3")
