@@ -30,7 +30,8 @@ Also reported on the same line:
                     face gradient of 0.5*|u - u_t|^2); temporally blocked
                     Jacobi (4096^2, 64 iterations); pentadiagonal line
                     solves (162^3, x, y, z); the 27-point ILU (256^3);
-                    the x-line scan variant of the 27-point sweep (256^3).
+                    the x-line scan variant of the 27-point sweep (256^3);
+                    the 27-point sweep and SpMV at 512^3 (beyond the MALL).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 2]
     python bench.py --roofline-only      (kernel loops only, for profiling)
@@ -93,9 +94,10 @@ def parse():
                     help="skip the workloads beside the 27-point sweep")
     ap.add_argument("--workloads-only", action="store_true",
                     help="only the workloads beside the 27-point sweep")
-    ap.add_argument("--workloads", default="ssor,var7,jacobi,penta,ilu,xline",
+    ap.add_argument("--workloads",
+                    default="ssor,var7,jacobi,penta,ilu,xline,probe512",
                     help="which of them: ssor, var7, jacobi, penta, ilu, "
-                         "xline (comma-separated)")
+                         "xline, probe512 (comma-separated)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the kernel loops and a copy calibration")
     return ap.parse_args()
@@ -122,7 +124,7 @@ def flops_per_iteration(n, levels):
 
 def extra_workloads(torch, m, inputs, dev, reps,
                     which=("ssor", "var7", "jacobi", "penta", "ilu",
-                           "xline")):
+                           "xline", "probe512")):
     """The workloads beside the 27-point sweep, by name."""
     out = {}
     if "ssor" in which:
@@ -137,7 +139,38 @@ def extra_workloads(torch, m, inputs, dev, reps,
         out.update(ilu_workload(torch, m, inputs, dev, reps))
     if "xline" in which:
         out.update(xline_workload(torch, m, inputs, dev, reps))
+    if "probe512" in which:
+        out.update(probe512_workload(torch, m, inputs, dev, reps))
     return out
+
+
+def probe512_workload(torch, m, inputs, dev, reps):
+    """The 27-point sweep and SpMV at 512^3 FP64 (1.07 GB per vector, four
+    times the 256 MB MALL): a size whose vectors cannot stay cache-resident,
+    so the GB/s figures are HBM figures."""
+    n = 512
+    shape = (n, n, n)
+    npts = n ** 3
+    A = m.const27(shape)
+    ws = m.Workspace(A)
+    r = torch.from_numpy(inputs.standard_normal(12, shape)).to(dev)
+    x0 = torch.from_numpy(inputs.standard_normal(13, shape)).to(dev)
+    x1 = torch.empty_like(x0)
+    m.symgs_oop(A, r, x0, x1, "fwd", ws)
+    fwd = event_ms(torch, lambda: m.symgs_oop(A, r, x0, x1, "fwd", ws), reps)
+    ws.check()
+    m.spmv(A, x0, x1)
+    spmv = event_ms(torch, lambda: m.spmv(A, x0, x1), reps)
+    sg, pg = 24 * npts / (fwd * 1e-3) / 1e9, 16 * npts / (spmv * 1e-3) / 1e9
+    log(f"512^3 probe: sweep fwd {fwd:.3f} ms ({sg:.0f} GB/s), "
+        f"spmv {spmv:.3f} ms ({pg:.0f} GB/s)")
+    return {"probe_512": {
+        "workload": "27-point 26/-1 operator at 512^3 FP64 (larger than "
+                    "the MALL), r, x ~ N(0,1) seeds 12, 13",
+        "sweep_fwd_ms": fwd, "sweep_achieved": sg, "sweep_frac":
+        sg / HBM_PEAK_GBS, "spmv_ms": spmv, "spmv_achieved": pg,
+        "spmv_frac": pg / HBM_PEAK_GBS,
+        "unit": "GB/s (sweep 24 B per point, SpMV 16 B per point)"}}
 
 
 def xline_workload(torch, m, inputs, dev, reps):

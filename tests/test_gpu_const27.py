@@ -123,3 +123,18 @@ def test_full_size_symgs(m, n):
     assert rel_inf(out, ref) <= 1e-13
     y = host(m.spmv(A, dev(x0)))
     assert rel_inf(y, oracle.spmv27(x0)) <= 1e-13
+
+
+def test_full_size_symgs_512_forward(m):
+    # the larger-than-MALL probe size (1.07 GB per vector), compared point
+    # by point; the deepest buffer offsets the sweep kernels form
+    shape = (512, 512, 512)
+    banner(f"symgs27 full size {shape} fwd")
+    A = m.const27(shape)
+    r = inputs.standard_normal(12, shape)
+    x0 = inputs.standard_normal(13, shape)
+    out = torch.empty(shape, dtype=torch.float64, device="cuda")
+    m.symgs_oop(A, dev(r), dev(x0), out, "fwd")
+    got = host(out)
+    del out
+    assert rel_inf(got, oracle.symgs27(r, x0, "fwd")) <= 1e-13
