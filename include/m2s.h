@@ -160,11 +160,15 @@ m2s_status m2s_symgs_oop(const m2s_stencil *A, const void *r,
  * recurrence x_i = g_i - (a_off / a_pp) x_{i-1} is solved by a parallel
  * prefix scan of affine maps.  Same update as m2s_symgs (in place, same
  * dir values, same workspace), but the scan regroups the sums: the result
- * equals the lexicographic sweep only up to rounding, not bitwise.
- * Returns M2S_ERR_UNSUPPORTED for other kinds, M2S_ERR_DTYPE for F32,
- * M2S_ERR_SHAPE when nx > 3840 (the line does not fit the scan's LDS),
- * M2S_ERR_ALIAS if r and x overlap.  A dependency wait that times out
- * latches M2S_ERR_TIMEOUT (read by m2s_check). */
+ * equals the lexicographic sweep only up to rounding, not bitwise.  The
+ * first call on a workspace allocates a 16-byte record per grid point in
+ * it (the planes hand their new values to each other through them; freed
+ * with the workspace).  Returns M2S_ERR_UNSUPPORTED for other kinds,
+ * M2S_ERR_DTYPE for F32, M2S_ERR_SHAPE when nx > 4094 (the line does not
+ * fit the scan's LDS) or nx*ny*nz >= 2^28, M2S_ERR_ALIAS if r and x
+ * overlap, M2S_ERR_HIP if the record array cannot be allocated.  A
+ * dependency wait that times out latches M2S_ERR_TIMEOUT (read by
+ * m2s_check). */
 m2s_status m2s_symgs_xline(const m2s_stencil *A, const void *r, void *x,
                            m2s_dir dir, m2s_workspace *ws, hipStream_t stream);
 

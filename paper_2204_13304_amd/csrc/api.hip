@@ -20,11 +20,11 @@ hipError_t launch_sweep_sequential_b7(const m2s_stencil &A,
                                       const void *b, void *x, bool bwd,
                                       hipStream_t s);
 // k_xline.hip: line-scheduled 27-point half-sweep with the x-line scan
-// (FP64); flags holds nz 64-bit words.
+// (FP64); rec holds one 16-byte record per point.
 size_t xline_lds_bytes(int nx);
 hipError_t launch_xline_sweep(const m2s_stencil &A, const void *r,
                               const void *xin, void *xout, bool bwd,
-                              Workspace &ws, uint64_t *flags, hipStream_t s);
+                              Workspace &ws, void *rec, hipStream_t s);
 
 // LU with partial pivoting of the 5x5 centre block (row-major), host side.
 hipError_t fill_block7_consts(const double *blocks, Block7Consts &C)
@@ -91,7 +91,11 @@ void set_block7_omega(Block7Consts &C, double omega)
 }
 }  // namespace m2s
 
-struct m2s_workspace : public Workspace {};
+struct m2s_workspace : public Workspace {
+    // line-scheduled 27-point sweep: one 16-byte record per point, made on
+    // the first such call (zeroed: epoch 0 is never a launch's)
+    void *xl_rec = nullptr;
+};
 
 namespace {
 
@@ -436,6 +440,7 @@ void m2s_workspace_destroy(m2s_workspace *ws)
     if (ws->bnd) (void)hipFree(ws->bnd);
     if (ws->tile_list) (void)hipFree(ws->tile_list);
     if (ws->b7c) (void)hipFree(ws->b7c);
+    if (ws->xl_rec) (void)hipFree(ws->xl_rec);
     delete ws;
 }
 
@@ -552,20 +557,27 @@ m2s_status m2s_symgs_xline(const m2s_stencil *A, const void *r, void *x,
     if (!r || !x) return M2S_ERR_ARG;
     if (dir != M2S_FWD && dir != M2S_BWD && dir != M2S_SYM) return M2S_ERR_ARG;
     if ((st = check_ws(*A, ws)) != M2S_OK) return st;
-    if (xline_lds_bytes(A->ext.nx) > 64 * 1024) return M2S_ERR_SHAPE;
+    if (xline_lds_bytes(A->ext.nx) > 160 * 1024 - 64) return M2S_ERR_SHAPE;
+    // records are addressed with 32-bit byte offsets
+    const uint64_t rec_bytes = 16ull * (uint64_t)npoints(*A);
+    if (rec_bytes >= (1ull << 32)) return M2S_ERR_SHAPE;
     const size_t vb = (size_t)npoints(*A) * elem_size(*A);
     if (overlap(r, x, vb)) return M2S_ERR_ALIAS;
-    // the per-plane progress words live in the second scratch vector
-    // (nz words <= the vector's nx ny nz doubles)
-    uint64_t *flags = (uint64_t *)ws->scratch2;
+    if (!ws->xl_rec) {
+        if (hipMalloc(&ws->xl_rec, rec_bytes) != hipSuccess) {
+            ws->xl_rec = nullptr;
+            return M2S_ERR_HIP;
+        }
+        M2S_TRY(hipMemsetAsync(ws->xl_rec, 0, rec_bytes, stream));
+    }
     if (dir == M2S_SYM) {
-        M2S_TRY(launch_xline_sweep(*A, r, x, ws->scratch, false, *ws, flags,
-                                   stream));
+        M2S_TRY(launch_xline_sweep(*A, r, x, ws->scratch, false, *ws,
+                                   ws->xl_rec, stream));
         return hip_status(launch_xline_sweep(*A, r, ws->scratch, x, true, *ws,
-                                             flags, stream));
+                                             ws->xl_rec, stream));
     }
     M2S_TRY(launch_xline_sweep(*A, r, x, ws->scratch, dir == M2S_BWD, *ws,
-                               flags, stream));
+                               ws->xl_rec, stream));
     return hip_status(launch_copy(x, ws->scratch, (int64_t)vb, stream));
 }
 

@@ -76,8 +76,8 @@ def test_xline_rejects_other_kinds_and_f32(m):
     x = torch.zeros((8, 8, 8), dtype=torch.float32, device="cuda")
     with pytest.raises(RuntimeError):
         m.symgs_xline(A32, x.clone(), x)
-    A = m.const27((4, 4, 4000))
-    x = torch.zeros((4, 4, 4000), dtype=torch.float64, device="cuda")
+    A = m.const27((4, 4, 5000))
+    x = torch.zeros((4, 4, 5000), dtype=torch.float64, device="cuda")
     with pytest.raises(RuntimeError):
         m.symgs_xline(A, x.clone(), x)
 
