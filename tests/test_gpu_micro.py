@@ -76,8 +76,10 @@ def _penta(shape, seed):
 
 @pytest.mark.parametrize("axis", ["x", "y", "z"])
 @pytest.mark.parametrize("shape", [(7, 9, 11), (1, 1, 1), (3, 65, 2),
-                                   (33, 4, 70)])
+                                   (33, 4, 70), (5, 3, 400), (300, 2, 3)])
 def test_penta_lines_parity(m, axis, shape):
+    # ragged and single-point lines, and long ones (400 along x, 300 along
+    # z): many 16-point chunks with a ragged last one
     banner(f"penta {axis} {shape}")
     coef, r = _penta(shape, 40)
     x = m.penta_lines(dev(coef), dev(r), axis)
