@@ -17,7 +17,8 @@ Also reported on the same line:
   roofline          the exact lexicographic SymGS wavefront kernel at 256^3
                     (forward and backward half-sweeps out of place,
                     algorithmic 24 B per point), timed with HIP events on
-                    the stream it runs on, against 8 TB/s;
+                    the stream it runs on, against 8 TB/s and against the
+                    rate of a 1 GiB device copy measured in the same run;
   spmv              the 27-point SpMV kernel (16 B per point) likewise;
   time_to_solution  FP64 MG-PCG and mixed MG-PCG (V-cycle in FP32, CG in
                     FP64) to relative residual 1e-9 from x0 = 0;
@@ -409,6 +410,18 @@ def roofline_loops(torch, m, inputs, n, reps, dev):
         spmv_gflops=2 * nnz27(n) / (spmv * 1e-3) / 1e9)
 
 
+def copy_bandwidth(torch, dev, reps):
+    """A 1 GiB device-to-device copy (read + write bytes / time): the HBM
+    rate a plain streaming kernel reaches on this GPU, beside the nominal
+    8 TB/s."""
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    ms = event_ms(torch, lambda: dst.copy_(src), reps)
+    del src, dst
+    return 2 * (8 << 27) / (ms * 1e-3) / 1e9
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -439,13 +452,17 @@ def main():
     log(f"sweep fwd {rl['fwd_ms']:.3f} ms bwd {rl['bwd_ms']:.3f} ms "
         f"({rl['sweep_gbs']:.0f} GB/s); spmv {rl['spmv_ms']:.3f} ms "
         f"({rl['spmv_gbs']:.0f} GB/s); fp32 fwd {rl['fwd32_ms']:.3f} ms")
+    copy_gbs = copy_bandwidth(torch, dev, args.reps)
+    log(f"device copy (1 GiB each way): {copy_gbs:.0f} GB/s")
     roof = {"bound": "hbm", "achieved": rl["sweep_gbs"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": rl["sweep_gbs"] / HBM_PEAK_GBS,
             "traffic": measured_traffic(),
             "kernel": f"c27_tile_kernel<double> (fwd and bwd) at {n}^3, "
                       "24 B/point",
             "avg_ms": rl["sweep_ms"], "fwd_ms": rl["fwd_ms"],
-            "bwd_ms": rl["bwd_ms"]}
+            "bwd_ms": rl["bwd_ms"],
+            "measured_copy_gbs": copy_gbs,
+            "frac_of_measured_copy": rl["sweep_gbs"] / copy_gbs}
     if args.roofline_only:
         # a plain copy of known size, for scaling the HBM byte counters
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
@@ -552,6 +569,7 @@ def main():
         "spmv": {"achieved": rl["spmv_gbs"], "unit": "GB/s",
                  "avg_ms": rl["spmv_ms"],
                  "frac": rl["spmv_gbs"] / HBM_PEAK_GBS,
+                 "frac_of_measured_copy": rl["spmv_gbs"] / copy_gbs,
                  "gflops": rl["spmv_gflops"]},
         "symgs_gflops": rl["symgs_gflops"],
         "sweep_fp32": {"avg_ms": rl["fwd32_ms"], "achieved": rl["fwd32_gbs"],
