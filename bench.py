@@ -85,7 +85,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--levels", type=int, default=4)
-    ap.add_argument("--reps", type=int, default=10,
+    ap.add_argument("--reps", type=int, default=20,
                     help="launches per kernel in the roofline loops")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU-oracle baseline")
@@ -375,6 +375,24 @@ def event_ms(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def event_stats(torch, fn, reps, warm=3):
+    """(mean, median) duration in ms of fn() over reps launches after warm
+    untimed ones; a HIP event is recorded on torch's current stream (the
+    stream the library launches on) between consecutive launches."""
+    for _ in range(warm):
+        fn()
+    s = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(s)
+    for q in range(reps):
+        fn()
+        ev[q + 1].record(s)
+    ev[-1].synchronize()
+    d = sorted(ev[q].elapsed_time(ev[q + 1]) for q in range(reps))
+    med = d[reps // 2] if reps % 2 else 0.5 * (d[reps // 2 - 1] + d[reps // 2])
+    return sum(d) / reps, med
+
+
 def roofline_loops(torch, m, inputs, n, reps, dev):
     shape = (n, n, n)
     npts = n ** 3
@@ -383,26 +401,28 @@ def roofline_loops(torch, m, inputs, n, reps, dev):
     r = torch.from_numpy(inputs.standard_normal(10, shape)).to(dev)
     x0 = torch.from_numpy(inputs.standard_normal(11, shape)).to(dev)
     x1 = torch.empty_like(x0)
-    for d in ("fwd", "bwd"):
-        m.symgs_oop(A, r, x0, x1, d, ws)  # warm
-    fwd = event_ms(torch, lambda: m.symgs_oop(A, r, x0, x1, "fwd", ws), reps)
-    bwd = event_ms(torch, lambda: m.symgs_oop(A, r, x0, x1, "bwd", ws), reps)
+    # 3 warm-up launches, then reps launches each timed with events; the
+    # means give the roofline (they compare with a profiler's average
+    # duration), the medians are reported beside them
+    fwd, fwd_med = event_stats(
+        torch, lambda: m.symgs_oop(A, r, x0, x1, "fwd", ws), reps)
+    bwd, bwd_med = event_stats(
+        torch, lambda: m.symgs_oop(A, r, x0, x1, "bwd", ws), reps)
     ws.check()
-    m.spmv(A, x0, x1)
-    spmv = event_ms(torch, lambda: m.spmv(A, x0, x1), reps)
+    spmv, spmv_med = event_stats(torch, lambda: m.spmv(A, x0, x1), reps)
     # the same sweep in FP32 (the mixed-precision V-cycle's level 0)
     A32 = m.const27(shape, dtype=torch.float32)
     ws32 = m.Workspace(A32)
     r32, x032 = r.float(), x0.float()
     x132 = torch.empty_like(x032)
-    m.symgs_oop(A32, r32, x032, x132, "fwd", ws32)
-    fwd32 = event_ms(torch, lambda: m.symgs_oop(A32, r32, x032, x132, "fwd",
-                                                 ws32), reps)
+    fwd32, _ = event_stats(
+        torch, lambda: m.symgs_oop(A32, r32, x032, x132, "fwd", ws32), reps)
     ws32.check()
     sweep_ms = 0.5 * (fwd + bwd)
     return dict(
         sweep_ms=sweep_ms, fwd_ms=fwd, bwd_ms=bwd, spmv_ms=spmv,
-        fwd32_ms=fwd32,
+        fwd32_ms=fwd32, sweep_median_ms=0.5 * (fwd_med + bwd_med),
+        spmv_median_ms=spmv_med,
         sweep_gbs=24 * npts / (sweep_ms * 1e-3) / 1e9,
         spmv_gbs=16 * npts / (spmv * 1e-3) / 1e9,
         fwd32_gbs=12 * npts / (fwd32 * 1e-3) / 1e9,
@@ -447,7 +467,8 @@ def main():
             torch, m, inputs, dev, args.reps, args.workloads.split(","))}))
         return 0
 
-    log(f"roofline loops at {n}^3, {args.reps} launches each")
+    log(f"roofline loops at {n}^3: 3 warm-up and {args.reps} timed "
+        "launches each")
     rl = roofline_loops(torch, m, inputs, n, args.reps, dev)
     log(f"sweep fwd {rl['fwd_ms']:.3f} ms bwd {rl['bwd_ms']:.3f} ms "
         f"({rl['sweep_gbs']:.0f} GB/s); spmv {rl['spmv_ms']:.3f} ms "
@@ -459,8 +480,8 @@ def main():
             "traffic": measured_traffic(),
             "kernel": f"c27_tile_kernel<double> (fwd and bwd) at {n}^3, "
                       "24 B/point",
-            "avg_ms": rl["sweep_ms"], "fwd_ms": rl["fwd_ms"],
-            "bwd_ms": rl["bwd_ms"],
+            "avg_ms": rl["sweep_ms"], "median_ms": rl["sweep_median_ms"],
+            "fwd_ms": rl["fwd_ms"], "bwd_ms": rl["bwd_ms"],
             "measured_copy_gbs": copy_gbs,
             "frac_of_measured_copy": rl["sweep_gbs"] / copy_gbs}
     if args.roofline_only:
@@ -567,7 +588,7 @@ def main():
                    "grid": [n, n, n], "levels": L},
         "roofline": roof,
         "spmv": {"achieved": rl["spmv_gbs"], "unit": "GB/s",
-                 "avg_ms": rl["spmv_ms"],
+                 "avg_ms": rl["spmv_ms"], "median_ms": rl["spmv_median_ms"],
                  "frac": rl["spmv_gbs"] / HBM_PEAK_GBS,
                  "frac_of_measured_copy": rl["spmv_gbs"] / copy_gbs,
                  "gflops": rl["spmv_gflops"]},
