@@ -445,9 +445,9 @@ def copy_bandwidth(torch, dev, reps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
-                          "--gpus must be 1 (how the path would shard over "
-                          "several GPUs is described in DESIGN.md)"}))
+        print(json.dumps({"error": "runs on one GPU only: --gpus must be "
+                          "1 (sharding the sweeps over several GPUs, as "
+                          "z-slab pipelines, is not built)"}))
         return 2
     import numpy as np  # noqa: F401
     import torch
