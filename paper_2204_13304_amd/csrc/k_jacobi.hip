@@ -14,7 +14,10 @@
 // Each thread owns one column of the region and a contiguous range of its
 // rows; it walks down the rows keeping the three-value row sums of the
 // previous and current row in registers, so a point costs three LDS reads.
-// One workgroup per CU (the two iterate buffers and b fill the LDS).
+// The two iterate buffers and b fill a CU's LDS, so one workgroup per CU:
+// the launch is persistent (one workgroup per CU walking the tiles), and
+// the next tile's x and b region is loaded into registers while the
+// current tile iterates, so that loads and LDS work overlap.
 #include "m2s_internal.hpp"
 
 #include <algorithm>
@@ -27,7 +30,8 @@ constexpr int J9_NT = 1024;  // threads per workgroup: 16 wavefronts hide the
 
 template <int H>
 __global__ void __launch_bounds__(J9_NT)
-    jacobi9_tb_kernel(int nx, int ny, double inv_diag, double off,
+    jacobi9_tb_kernel(int nx, int ny, int tiles_x, int ntiles,
+                      double inv_diag, double off,
                       const double *__restrict__ b,
                       const double *__restrict__ xin,
                       double *__restrict__ xout)
@@ -38,76 +42,90 @@ __global__ void __launch_bounds__(J9_NT)
     double *const xa = sm;
     double *const xb = sm + W * W;
     double *const bs = sm + 2 * W * W;
-    const int gx0 = blockIdx.x * J9_TS - H, gy0 = blockIdx.y * J9_TS - H;
     const int tid = threadIdx.x;
 
-    // all of a thread's loads first (many in flight), then the LDS stores
+    // a tile's x and b region, W^2 values each, NL per thread: loaded into
+    // registers while the previous tile computes, then written to LDS
     constexpr int NL = (W * W + J9_NT - 1) / J9_NT;
     double vx[NL], vb[NL];
+    auto fetch = [&](int tile) {
+        const int gx0 = (tile % tiles_x) * J9_TS - H;
+        const int gy0 = (tile / tiles_x) * J9_TS - H;
 #pragma unroll
-    for (int q = 0; q < NL; ++q) {
-        const int e = tid + q * J9_NT;
-        const int ly = e / W, lx = e - (e / W) * W;
-        const int gx = gx0 + lx, gy = gy0 + ly;
-        const bool in =
-            e < W * W && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-        const long g = in ? (long)gy * nx + gx : 0;
-        vx[q] = in ? xin[g] : 0.0;
-        vb[q] = in ? b[g] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-        const int e = tid + q * J9_NT;
-        if (e < W * W) {
-            xa[e] = vx[q];
-            bs[e] = vb[q];
+        for (int q = 0; q < NL; ++q) {
+            const int e = tid + q * J9_NT;
+            const int ly = e / W, lx = e - (e / W) * W;
+            const int gx = gx0 + lx, gy = gy0 + ly;
+            const bool in =
+                e < W * W && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+            const long g = in ? (long)gy * nx + gx : 0;
+            vx[q] = in ? xin[g] : 0.0;
+            vb[q] = in ? b[g] : 0.0;
         }
-    }
-    __syncthreads();
+    };
 
-    const int c = tid % W, grp = tid / W;
-    const int gx = gx0 + c;
-    const bool colin = gx >= 0 && gx < nx;
-#pragma unroll 1
-    for (int t = 1; t <= H; ++t) {
-        const double *src = (t & 1) ? xa : xb;
-        double *dst = (t & 1) ? xb : xa;
-        const int lo = t, hi = W - t;  // rows and columns computed
-        const int rows = (hi - lo + G - 1) / G;
-        const int r0 = lo + grp * rows, r1 = min(hi, r0 + rows);
-        if (grp < G && c >= lo && c < hi && r0 < r1) {
-            auto row3 = [&](int r, double &s3, double &side) {
-                const double *q = src + r * W + c;
-                const double l = q[-1], m = q[0], rr = q[1];
-                side = l + rr;
-                s3 = side + m;
-            };
-            double sp, spd, sc, scd;
-            row3(r0 - 1, sp, spd);
-            row3(r0, sc, scd);
-#pragma unroll 4
-            for (int r = r0; r < r1; ++r) {
-                double sn, snd;
-                row3(r + 1, sn, snd);
-                const double sum = (sp + scd) + sn;
-                const int gy = gy0 + r;
-                const bool in = colin && gy >= 0 && gy < ny;
-                dst[r * W + c] = in ? (bs[r * W + c] - off * sum) * inv_diag
-                                    : 0.0;
-                sp = sc;
-                sc = sn;
-                scd = snd;
+    int tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    fetch(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const int gx0 = (tile % tiles_x) * J9_TS - H;
+        const int gy0 = (tile / tiles_x) * J9_TS - H;
+        __syncthreads();  // the previous tile's result has left the LDS
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const int e = tid + q * J9_NT;
+            if (e < W * W) {
+                xa[e] = vx[q];
+                bs[e] = vb[q];
             }
         }
         __syncthreads();
-    }
+        if (tile + (int)gridDim.x < ntiles) fetch(tile + gridDim.x);
 
-    const double *fin = (H & 1) ? xb : xa;
-    for (int e = tid; e < J9_TS * J9_TS; e += J9_NT) {
-        const int ly = e / J9_TS, lx = e % J9_TS;
-        const int ox = gx0 + H + lx, oy = gy0 + H + ly;
-        if (ox < nx && oy < ny)
-            xout[(long)oy * nx + ox] = fin[(ly + H) * W + lx + H];
+        const int c = tid % W, grp = tid / W;
+        const int gx = gx0 + c;
+        const bool colin = gx >= 0 && gx < nx;
+#pragma unroll 1
+        for (int t = 1; t <= H; ++t) {
+            const double *src = (t & 1) ? xa : xb;
+            double *dst = (t & 1) ? xb : xa;
+            const int lo = t, hi = W - t;  // rows and columns computed
+            const int rows = (hi - lo + G - 1) / G;
+            const int r0 = lo + grp * rows, r1 = min(hi, r0 + rows);
+            if (grp < G && c >= lo && c < hi && r0 < r1) {
+                auto row3 = [&](int r, double &s3, double &side) {
+                    const double *q = src + r * W + c;
+                    const double l = q[-1], m = q[0], rr = q[1];
+                    side = l + rr;
+                    s3 = side + m;
+                };
+                double sp, spd, sc, scd;
+                row3(r0 - 1, sp, spd);
+                row3(r0, sc, scd);
+#pragma unroll 4
+                for (int r = r0; r < r1; ++r) {
+                    double sn, snd;
+                    row3(r + 1, sn, snd);
+                    const double sum = (sp + scd) + sn;
+                    const int gy = gy0 + r;
+                    const bool in = colin && gy >= 0 && gy < ny;
+                    dst[r * W + c] =
+                        in ? (bs[r * W + c] - off * sum) * inv_diag : 0.0;
+                    sp = sc;
+                    sc = sn;
+                    scd = snd;
+                }
+            }
+            __syncthreads();
+        }
+
+        const double *fin = (H & 1) ? xb : xa;
+        for (int e = tid; e < J9_TS * J9_TS; e += J9_NT) {
+            const int ly = e / J9_TS, lx = e % J9_TS;
+            const int ox = gx0 + H + lx, oy = gy0 + H + ly;
+            if (ox < nx && oy < ny)
+                xout[(long)oy * nx + ox] = fin[(ly + H) * W + lx + H];
+        }
     }
 }
 
@@ -126,9 +144,18 @@ static hipError_t jacobi9_pass(int nx, int ny, double inv_diag, double off,
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    dim3 grid((nx + J9_TS - 1) / J9_TS, (ny + J9_TS - 1) / J9_TS);
-    hipLaunchKernelGGL(jacobi9_tb_kernel<H>, grid, dim3(J9_NT), lds, s, nx,
-                       ny, inv_diag, off, b, xin, xout);
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                  dev);
+    if (e != hipSuccess) return e;
+    const int tiles_x = (nx + J9_TS - 1) / J9_TS;
+    const int ntiles = tiles_x * ((ny + J9_TS - 1) / J9_TS);
+    // persistent: one workgroup per CU walks tiles blockIdx.x + k gridDim.x
+    const int grid = std::max(1, std::min(ntiles, cus));
+    hipLaunchKernelGGL(jacobi9_tb_kernel<H>, dim3(grid), dim3(J9_NT), lds, s,
+                       nx, ny, tiles_x, ntiles, inv_diag, off, b, xin, xout);
     return hipGetLastError();
 }
 
