@@ -91,7 +91,7 @@ def _fake_var7(m, shape):
 # written by one wavefront and touched by another in the same step; and
 # every point must be stored exactly once, with its new value.
 # ---------------------------------------------------------------------------
-TU, RU, W, WR, POLL, PRE = 16, 20, 32, 16, 4, 18
+TU, RU, W, WR, PRE = 16, 20, 32, 16, 18
 
 
 def c27_tile_list(shape, kt):
@@ -106,7 +106,7 @@ def c27_tile_list(shape, kt):
     return out
 
 
-def simulate_c27_tiles(shape, nw, zero_start=False):
+def simulate_c27_tiles(shape, nw, zero_start=False, POLL=4):
     """Wavefronts 0 .. nw-1 compute (one lane per row), nw .. 2nw-1 memory
     (wavefront nw + m stages x_old / r of compute wavefront m's rows and
     stores its pieces), 2nw polls the neighbour tiles' boundary records."""
@@ -269,8 +269,11 @@ def simulate_c27_tiles(shape, nw, zero_start=False):
 @pytest.mark.parametrize("shape", [(9, 7, 6), (5, 3, 11), (6, 20, 37),
                                    (13, 5, 4), (17, 18, 3), (1, 1, 1)])
 @pytest.mark.parametrize("nw", [1, 2, 4])
-def test_c27_tile_model(shape, nw):
-    simulate_c27_tiles(shape, nw)
+@pytest.mark.parametrize("poll", [2, 4])
+def test_c27_tile_model(shape, nw, poll):
+    # the kernel polls 2 steps ahead when every tile has a workgroup of its
+    # own and 4 otherwise
+    simulate_c27_tiles(shape, nw, POLL=poll)
 
 
 def test_c27_tile_model_zero_start():
