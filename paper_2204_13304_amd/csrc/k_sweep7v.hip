@@ -26,7 +26,7 @@
 //  * The arithmetic is v7_combine, shared with the sequential kernel.
 //  * Boundary rows (j0 + 15 of every plane, j0 .. j0 + 14 of the top
 //    plane) publish one epoch-tagged record per step; consumers poll them
-//    4 steps ahead.
+//    2 or 4 steps ahead (v7_poll).
 #include "m2s_internal.hpp"
 #include "tile_common.hpp"
 
@@ -38,7 +38,11 @@ namespace m2s {
 constexpr int V7_TJ = 16;    // j-rows per tile
 constexpr int V7_RJ = 18;    // x-ring rows per plane: jj = -1 .. 16
 constexpr int V7_W = 8;      // ring columns
-constexpr int V7_POLL = 4;   // boundary poll distance (steps)
+// Boundary poll distance (steps; a template parameter, 2 or 4): a consumer
+// tile settles about POLL steps plus a round trip behind its neighbour, so
+// 2 where every tile has a workgroup of its own and crossings are the
+// critical path, 4 where tiles queue for workgroups.
+inline int v7_poll(int ntiles, int grid) { return ntiles <= grid ? 2 : 4; }
 constexpr int V7_PRE = 16;   // steps before the smallest row skew
 
 template <typename T>
@@ -58,7 +62,7 @@ struct V7Args {
     int spin_limit;
 };
 
-template <typename T, bool BWD, int NW>
+template <typename T, bool BWD, int NW, int POLL>
 __global__ void __launch_bounds__(64 * (2 * NW + 1))
     v7_tile_kernel(V7Args<T> a)
 {
@@ -346,9 +350,9 @@ __global__ void __launch_bounds__(64 * (2 * NW + 1))
                 const int s = min(max(T_ - hT0, 0), a.ns - 1);
                 return hslot + s * WB;
             };
-            typename R::V ppipe[V7_POLL];
+            typename R::V ppipe[POLL];
 #pragma unroll
-            for (int p = 0; p < V7_POLL; ++p) ppipe[p] = typename R::V{};
+            for (int p = 0; p < POLL; ++p) ppipe[p] = typename R::V{};
             int spin_budget = a.spin_limit;
             for (int blk = 0; blk < nblk; ++blk) {
                 const int Tb = T_start + 16 * blk;
@@ -361,7 +365,7 @@ __global__ void __launch_bounds__(64 * (2 * NW + 1))
                     if (hv && c >= 0) {
                         T v = T(0);
                         if (c < nx) {
-                            typename R::V rec = ppipe[ph & (V7_POLL - 1)];
+                            typename R::V rec = ppipe[ph & (POLL - 1)];
                             const unsigned src = (unsigned)pslice(st) * RB;
                             while (!R::ready(rec, ep)) {
                                 if (--spin_budget < 0 ||
@@ -381,9 +385,9 @@ __global__ void __launch_bounds__(64 * (2 * NW + 1))
                         }
                         hrow[c & (V7_W - 1)] = v;
                     }
-                    ppipe[ph & (V7_POLL - 1)] = R::load(
+                    ppipe[ph & (POLL - 1)] = R::load(
                         rs_b,
-                        hv ? (unsigned)pslice(st + V7_POLL) * RB : OOB);
+                        hv ? (unsigned)pslice(st + POLL) * RB : OOB);
                     __syncthreads();
                 }
                 if (s_abort) {
@@ -421,11 +425,11 @@ size_t v7_lds_bytes(int nw, m2s_dtype t)
 
 int v7_threads(int nw) { return 64 * (2 * nw + 1); }
 
-template <typename T, bool BWD, int NW>
-static hipError_t v7_launch_t(const V7Args<T> &a, int grid, size_t lds,
+template <typename T, bool BWD, int NW, int POLL>
+static hipError_t v7_launch_tp(const V7Args<T> &a, int grid, size_t lds,
                               hipStream_t s)
 {
-    auto k = v7_tile_kernel<T, BWD, NW>;
+    auto k = v7_tile_kernel<T, BWD, NW, POLL>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(
@@ -436,6 +440,15 @@ static hipError_t v7_launch_t(const V7Args<T> &a, int grid, size_t lds,
     }
     hipLaunchKernelGGL(k, dim3(grid), dim3(64 * (2 * NW + 1)), lds, s, a);
     return hipGetLastError();
+}
+
+template <typename T, bool BWD, int NW>
+static hipError_t v7_launch_t(const V7Args<T> &a, int grid, size_t lds,
+                              hipStream_t s)
+{
+    return v7_poll(a.ntiles, grid) == 2
+               ? v7_launch_tp<T, BWD, NW, 2>(a, grid, lds, s)
+               : v7_launch_tp<T, BWD, NW, 4>(a, grid, lds, s);
 }
 
 template <typename T>

@@ -499,10 +499,10 @@ def test_b7_plan_matches_tile_model(shape):
 # of neighbours outside the grid must give exactly 0 (they are multiplied by
 # boundary faces), and every face read must give that face.
 # ---------------------------------------------------------------------------
-V7_TJ, V7_W, V7_POLL, V7_PRE = 16, 8, 4, 16
+V7_TJ, V7_W, V7_PRE = 16, 8, 16
 
 
-def simulate_v7_tiles(shape, nw, zero_start=False):
+def simulate_v7_tiles(shape, nw, zero_start=False, V7_POLL=4):
     nz, ny, nx = shape
     KT = 4 * nw
     njt = -(-ny // V7_TJ)
@@ -649,8 +649,10 @@ def simulate_v7_tiles(shape, nw, zero_start=False):
 @pytest.mark.parametrize("shape", [(9, 7, 6), (5, 20, 11), (13, 17, 3),
                                    (1, 1, 1), (4, 33, 5), (17, 16, 4)])
 @pytest.mark.parametrize("nw", [1, 2, 4])
-def test_v7_tile_model(shape, nw):
-    simulate_v7_tiles(shape, nw)
+@pytest.mark.parametrize("poll", [2, 4])
+def test_v7_tile_model(shape, nw, poll):
+    # polls 2 steps ahead when every tile has a workgroup, else 4
+    simulate_v7_tiles(shape, nw, V7_POLL=poll)
 
 
 def test_v7_tile_model_zero_start():
