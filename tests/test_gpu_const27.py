@@ -68,6 +68,27 @@ def test_symgs_tile_height_bitwise(m, nw, monkeypatch):
     assert np.array_equal(host(xg), host(xs))
 
 
+@pytest.mark.parametrize("direction", ["fwd", "bwd"])
+def test_symgs_many_tiles_and_few_tiles_bitwise(m, direction):
+    # more tiles than workgroups (the sweep polls 4 steps ahead) on a thin
+    # grid, and few tiles (2 steps ahead): both bitwise equal to the
+    # sequential kernel and within 1e-13 of the oracle
+    for shape in ((200, 200, 5), (24, 24, 24)):
+        banner(f"symgs27 tile count {shape} {direction}")
+        A = m.const27(shape)
+        r = inputs.standard_normal(12, shape)
+        x0 = inputs.standard_normal(13, shape)
+        xg = dev(x0)
+        m.symgs(A, dev(r), xg, direction)
+        xs = dev(x0)
+        m.symgs_sequential(A, dev(r), xs, direction)
+        out = host(xg)
+        assert np.array_equal(out, host(xs))
+        assert rel_inf(out, oracle.symgs27(r, x0, direction)) <= 1e-13
+    assert m.plan_sweep(m.const27((200, 200, 5)))["nslabs"] > 256
+    assert m.plan_sweep(m.const27((24, 24, 24)))["nslabs"] <= 256
+
+
 def test_residual_identity(m):
     # (D + L) x_new + U x_old = r for a forward sweep, evaluated on the CPU
     shape = (12, 20, 18)

@@ -80,6 +80,28 @@ def test_symgs_var7_tiles_bitwise(m, direction, monkeypatch):
         assert np.array_equal(out, seq)
 
 
+@pytest.mark.parametrize("direction", ["fwd", "bwd"])
+def test_symgs_var7_many_tiles_bitwise(m, direction):
+    """More tiles than workgroups (9 j-tiles x 33 k-tiles on a thin grid):
+    the sweep then polls 4 steps ahead instead of 2; parity with the oracle
+    and bitwise equality with the sequential kernel."""
+    shape = (132, 132, 6)
+    banner(f"var7 many tiles {direction} {shape}")
+    pr = inputs.var7_problem(26, shape)
+    A = _A(m, pr)
+    r = inputs.standard_normal(7, shape)
+    x0 = inputs.standard_normal(8, shape)
+    ref = oracle.symgs_var7(r, x0, pr["kx"], pr["ky"], pr["kz"], direction)
+    xs = dev(x0)
+    m.symgs_sequential(A, dev(r), xs, direction)
+    xg = dev(x0)
+    m.symgs(A, dev(r), xg, direction)
+    out = host(xg)
+    assert m.plan_sweep(A)["nslabs"] > 256
+    assert rel_inf(out, ref) <= 1e-13
+    assert np.array_equal(out, host(xs))
+
+
 def test_var7_float32_tiles_bitwise(m):
     shape = (19, 35, 17)
     pr = inputs.var7_problem(25, shape)
