@@ -564,11 +564,14 @@ m2s_status m2s_symgs_xline(const m2s_stencil *A, const void *r, void *x,
     const size_t vb = (size_t)npoints(*A) * elem_size(*A);
     if (overlap(r, x, vb)) return M2S_ERR_ALIAS;
     if (!ws->xl_rec) {
-        if (hipMalloc(&ws->xl_rec, rec_bytes) != hipSuccess) {
-            ws->xl_rec = nullptr;
+        void *rec = nullptr;
+        if (hipMalloc(&rec, rec_bytes) != hipSuccess) return M2S_ERR_HIP;
+        // kept only once cleared: a later call relies on the zero epochs
+        if (hipMemsetAsync(rec, 0, rec_bytes, stream) != hipSuccess) {
+            (void)hipFree(rec);
             return M2S_ERR_HIP;
         }
-        M2S_TRY(hipMemsetAsync(ws->xl_rec, 0, rec_bytes, stream));
+        ws->xl_rec = rec;
     }
     if (dir == M2S_SYM) {
         M2S_TRY(launch_xline_sweep(*A, r, x, ws->scratch, false, *ws,
