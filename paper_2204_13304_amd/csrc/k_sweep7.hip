@@ -49,8 +49,10 @@ constexpr int B7_W = 16;     // x-ring columns
 constexpr int B7_RS = 81;    // x-ring row stride (doubles): 16 x 5 + 1
 constexpr int B7_BS = 41;    // b ring: 8 columns x 5 + 1
 constexpr int B7_US = 21;    // u and g rings: 4 columns x 5 + 1
-constexpr int B7_POLL = 2;   // boundary poll distance (steps): covers a
-                             // record round trip at this step time
+constexpr int B7_POLL = 1;   // boundary poll distance (steps): a step here
+                             // lasts about half a record round trip, and a
+                             // consumer settles about POLL steps plus a
+                             // round trip behind its neighbour
 constexpr int B7_PRE = 20;   // steps before the smallest row skew
 constexpr int B7_NT = 384;   // six wavefronts
 // Role of wavefront w.  The arithmetic roles issue the most instructions

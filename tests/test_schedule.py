@@ -326,7 +326,7 @@ def test_c27_plan_matches_tile_model(shape, monkeypatch):
 # by one wavefront in a step must not be touched by another in that step,
 # and every read a later value depends on must see the right value.
 # ---------------------------------------------------------------------------
-B7_TJ, B7_KT, B7_POLL, B7_PRE = 16, 4, 2, 20
+B7_TJ, B7_KT, B7_POLL, B7_PRE = 16, 4, 1, 20
 
 
 def simulate_b7_tiles(shape, zero_start=False):
