@@ -63,15 +63,17 @@ constexpr int C27_W = 32;     // x-ring columns
 constexpr int C27_WP = 33;    // padded x-ring stride
 constexpr int C27_WR = 16;    // r-ring columns
 constexpr int C27_WRP = 17;   // padded r-ring stride
-// Boundary poll distance (steps, a template parameter: 2 or 4).  The poll
-// wavefront loads the record of step T + POLL at step T.  A consumer tile
-// settles at a lag of about POLL steps plus one device-scope round trip
-// behind its neighbour, and every tile crossing on the critical path pays
-// that lag, so a short distance wins where crossings are all there is (every
-// tile has a workgroup of its own); where tiles queue for workgroups and the
-// tiles' steps are slower, 4 steps of slack keep a late record from
-// stalling the consumer a whole round trip.
-inline int c27_poll(int ntiles, int grid) { return ntiles <= grid ? 2 : 4; }
+// Boundary poll distance (steps).  The poll wavefront loads the record of
+// step T + C27_POLL at step T, into a ring of C27_PRING registers.  A
+// consumer tile settles at a lag of about the distance plus one
+// device-scope round trip behind its neighbour, and every tile crossing on
+// the critical path pays that lag; a shorter distance cuts it but lets a
+// record that arrives late stall the consumer a whole round trip.  3 steps
+// in a ring of 4 measured best overall (1 to 4 tried, with rings of 1, 2, 4).
+constexpr int C27_POLL = 3;
+constexpr int C27_PRING = 4;  // a power of 2 dividing the 16-step block
+static_assert(C27_POLL <= C27_PRING && 16 % C27_PRING == 0,
+              "a polled slot is checked before it is reloaded");
 constexpr int C27_PRE = 18;   // steps before the smallest row skew
 
 template <typename T>
@@ -119,7 +121,7 @@ __host__ __device__ inline int c27_slot(int ut, int vt, int KT, int nutb)
 //   1  ILU factor w = 1 / (diagc - off S)        (off = off^2, x is w)
 //   2  ILU lower  y = (r - off S) w
 //   3  ILU upper  z = r - off S w                (backward sweep, r = y)
-template <typename T, bool BWD, bool ZERO, int NW, int MODE, int POLL>
+template <typename T, bool BWD, bool ZERO, int NW, int MODE>
 __global__ void __launch_bounds__(64 * (2 * NW + 1))
     c27_tile_kernel(C27Args<T> a)
 {
@@ -376,9 +378,9 @@ __global__ void __launch_bounds__(64 * (2 * NW + 1))
                 const int q = min(max(T_ - T0p, 0), a.ns - 1);
                 return pbuf + q * WB;
             };
-            typename R::V ppipe[POLL];
+            typename R::V ppipe[C27_PRING];
 #pragma unroll
-            for (int q = 0; q < POLL; ++q) ppipe[q] = typename R::V{};
+            for (int q = 0; q < C27_PRING; ++q) ppipe[q] = typename R::V{};
             int spin_budget = a.spin_limit;
             for (int blk = 0; blk < nblk; ++blk) {
                 const int Tb = T_start + 16 * blk;
@@ -389,7 +391,7 @@ __global__ void __launch_bounds__(64 * (2 * NW + 1))
                     if (vh && c >= 0) {
                         T v = zero;
                         if (c < nx) {
-                            typename R::V rec = ppipe[ph & (POLL - 1)];
+                            typename R::V rec = ppipe[ph & (C27_PRING - 1)];
                             const unsigned src = (unsigned)pslice(st) * RB;
                             while (!R::ready(rec, ep)) {
                                 if (--spin_budget < 0 ||
@@ -409,9 +411,10 @@ __global__ void __launch_bounds__(64 * (2 * NW + 1))
                         }
                         hrow[c & (C27_W - 1)] = v;
                     }
-                    // poll the slice POLL steps ahead
-                    ppipe[ph & (POLL - 1)] = R::load(
-                        rs_b, vh ? (unsigned)pslice(st + POLL) * RB : OOB);
+                    // poll the slice C27_POLL steps ahead; its ring slot was
+                    // checked C27_PRING - C27_POLL steps ago
+                    ppipe[(ph + C27_POLL) & (C27_PRING - 1)] = R::load(
+                        rs_b, vh ? (unsigned)pslice(st + C27_POLL) * RB : OOB);
                     __syncthreads();
                 }
                 if (s_abort) {
@@ -461,11 +464,11 @@ size_t c27_lds_bytes(int nw, m2s_dtype t, int mode)
            es;
 }
 
-template <typename T, bool BWD, bool ZERO, int NW, int MODE, int POLL>
-static hipError_t c27_launch_tp(const C27Args<T> &a, int grid, size_t lds,
-                                hipStream_t s)
+template <typename T, bool BWD, bool ZERO, int NW, int MODE = 0>
+static hipError_t c27_launch_t(const C27Args<T> &a, int grid, size_t lds,
+                               hipStream_t s)
 {
-    auto k = c27_tile_kernel<T, BWD, ZERO, NW, MODE, POLL>;
+    auto k = c27_tile_kernel<T, BWD, ZERO, NW, MODE>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(
@@ -476,15 +479,6 @@ static hipError_t c27_launch_tp(const C27Args<T> &a, int grid, size_t lds,
     }
     hipLaunchKernelGGL(k, dim3(grid), dim3(64 * (2 * NW + 1)), lds, s, a);
     return hipGetLastError();
-}
-
-template <typename T, bool BWD, bool ZERO, int NW, int MODE = 0>
-static hipError_t c27_launch_t(const C27Args<T> &a, int grid, size_t lds,
-                               hipStream_t s)
-{
-    return c27_poll(a.ntiles, grid) == 2
-               ? c27_launch_tp<T, BWD, ZERO, NW, MODE, 2>(a, grid, lds, s)
-               : c27_launch_tp<T, BWD, ZERO, NW, MODE, 4>(a, grid, lds, s);
 }
 
 template <typename T, bool BWD, bool ZERO>

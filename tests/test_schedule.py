@@ -106,7 +106,7 @@ def c27_tile_list(shape, kt):
     return out
 
 
-def simulate_c27_tiles(shape, nw, zero_start=False, POLL=4):
+def simulate_c27_tiles(shape, nw, zero_start=False, POLL=3):
     """Wavefronts 0 .. nw-1 compute (one lane per row), nw .. 2nw-1 memory
     (wavefront nw + m stages x_old / r of compute wavefront m's rows and
     stores its pieces), 2nw polls the neighbour tiles' boundary records."""
@@ -269,11 +269,9 @@ def simulate_c27_tiles(shape, nw, zero_start=False, POLL=4):
 @pytest.mark.parametrize("shape", [(9, 7, 6), (5, 3, 11), (6, 20, 37),
                                    (13, 5, 4), (17, 18, 3), (1, 1, 1)])
 @pytest.mark.parametrize("nw", [1, 2, 4])
-@pytest.mark.parametrize("poll", [2, 4])
-def test_c27_tile_model(shape, nw, poll):
-    # the kernel polls 2 steps ahead when every tile has a workgroup of its
-    # own and 4 otherwise
-    simulate_c27_tiles(shape, nw, POLL=poll)
+def test_c27_tile_model(shape, nw):
+    # the kernel polls the boundary records 3 steps ahead
+    simulate_c27_tiles(shape, nw)
 
 
 def test_c27_tile_model_zero_start():
