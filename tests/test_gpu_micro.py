@@ -19,8 +19,10 @@ def m():
     return pkg
 
 
+# (300, 270): tiles whose whole region lies inside the grid at every fusion
+# depth (the kernel's path without the boundary select) beside boundary ones
 @pytest.mark.parametrize("shape", [(45, 70), (64, 64), (1, 1), (200, 130),
-                                   (257, 3)])
+                                   (257, 3), (300, 270)])
 @pytest.mark.parametrize("iters", [1, 5, 16])
 def test_jacobi9_parity_and_block_independence(m, shape, iters):
     banner(f"jacobi9 {shape} iters {iters}")
