@@ -100,13 +100,19 @@ const char *m2s_status_string(m2s_status s);
 int m2s_version(void);
 
 /* ---------------------------------------------------------------------
- * Workspace for the dependent sweeps: per-slab progress flags (monotone
- * epoch-tagged counters, never reset; the GPU analogue of the per-thread-
- * pair counters that Thm. 2 of Sec. 6.1 shows are sufficient), a ticket
- * counter that hands slabs to workgroups in dependency order, a device
- * error word and one scratch vector of the stencil's size (the out-of-place
- * target of a half-sweep).  Allocates device memory.  One workspace serves
- * one extent/kind/dtype; calls using it must be stream-ordered.
+ * Workspace for the dependent sweeps: a ticket counter that hands tiles to
+ * workgroups in dependency order; the tiles' boundary store, where each
+ * boundary value is published once per launch as a record tagged with the
+ * launch's epoch and polled by value by the dependent tiles (records are
+ * never reset: a new epoch tells new records from old ones; the GPU
+ * analogue of the monotone per-pair counters that Thm. 2 of Sec. 6.1 shows
+ * are sufficient); a device error word; and scratch vectors of the
+ * stencil's size (the out-of-place target of a half-sweep, adjoint
+ * chains).  Allocates device memory at creation; a sweep whose plan needs
+ * another tile layout (the tuning variables M2S_C27_WAVES / M2S_V7_WAVES
+ * changed since) rebuilds the boundary store synchronously, and the first
+ * m2s_symgs_xline call allocates that variant's record array.  One workspace serves one extent/kind/dtype;
+ * calls using it must be stream-ordered.
  * --------------------------------------------------------------------- */
 m2s_status m2s_workspace_create(const m2s_stencil *A, m2s_workspace **out);
 void m2s_workspace_destroy(m2s_workspace *ws);
