@@ -1,6 +1,8 @@
 """GPU parity of the multigrid V-cycle and the HPCG-form PCG against the
 oracle: V-cycle output (relative 1e-12), the 16^3 SymGS-PCG run to the known
-solution x = 1, the 104^3 4-level MG-PCG, mixed precision to 1e-9, and the
+solution x = 1, the 104^3 4-level MG-PCG, the 256^3 configuration the
+benchmark times (V-cycle and two iterations against the oracle, the FP64 and
+mixed solves to 1e-9 by their residuals), mixed precision to 1e-9, and the
 VAR7 MG-PCG."""
 import numpy as np
 import pytest
@@ -80,6 +82,61 @@ def test_pcg_mg_104(m):
     k = int(np.argmax(hr < 1e-10)) if np.any(hr < 1e-10) else len(hr)
     assert np.allclose(h[:k], hr[:k], rtol=1e-6, atol=0)
     assert rel_inf(x, ref["x"]) <= 1e-10
+
+
+def _bench_problem_256():
+    # the MG-PCG configuration the benchmark times: 256^3 CONST27, 4 levels,
+    # b = A*1 + N(0, 1e-3) with seed 3, x0 = 0
+    shape = (256, 256, 256)
+    b = oracle.spmv27(np.ones(shape)) + inputs.rhs_perturbation(3, shape)
+    return shape, b
+
+
+def test_vcycle_256(m):
+    shape, b = _bench_problem_256()
+    banner("vcycle 256^3 L=4")
+    mg = m.MG(m.const27(shape), 4)
+    z = host(mg.vcycle(dev(b)))
+    ref = oracle.MG("const27", shape, 4).vcycle(b)
+    assert rel_inf(z, ref) <= 1e-12
+
+
+def test_pcg_mg_256_two_iterations(m):
+    """The benchmark's configuration at full size: two iterations against
+    the oracle (which takes seconds per iteration there)."""
+    shape, b = _bench_problem_256()
+    banner("pcg mg 256^3, 2 iterations")
+    A = m.const27(shape)
+    mg = m.MG(A, 4)
+    x, info = m.pcg_solve(A, dev(b), None, "mg", mg, max_iter=2, rtol=0.0,
+                          history=True)
+    ref = oracle.pcg(b, precond="mg", levels=4, max_iter=2)
+    assert info["iters"] == 2
+    assert np.allclose(info["hist"], ref["hist"], rtol=1e-10, atol=0)
+    assert rel_inf(host(x), ref["x"]) <= 1e-10
+
+
+def test_pcg_256_to_tolerance_fp64_and_mixed(m):
+    """The benchmark's time-to-solution runs at 256^3 (rtol 1e-9; mixed:
+    FP32 V-cycle, residual replaced every 50 iterations).  The oracle cannot
+    run them to convergence at this size in a test, so they are checked by
+    what holds at any size: both reach a true FP64 residual <= 1e-9 within
+    a couple of iterations of each other, and agree to the accuracy the
+    tolerance allows."""
+    shape, b = _bench_problem_256()
+    banner("pcg mg 256^3 to 1e-9, fp64 and mixed")
+    A = m.const27(shape)
+    bd = dev(b)
+    out = {}
+    for tag, prec, rep in (("fp64", torch.float64, 0),
+                           ("mixed", torch.float32, 50)):
+        mg = m.MG(A, 4, prec=prec)
+        x, info = m.pcg_solve(A, bd, None, "mg", mg, max_iter=400, rtol=1e-9,
+                              replace_every=rep)
+        assert info["true_rel_res"] <= 1e-9, tag
+        out[tag] = (host(x), info["iters"])
+    assert abs(out["fp64"][1] - out["mixed"][1]) <= 2
+    assert rel_inf(out["mixed"][0], out["fp64"][0]) <= 1e-7
 
 
 def test_pcg_mixed_precision(m):
