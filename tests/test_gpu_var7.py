@@ -1,7 +1,8 @@
 """GPU parity of the VAR7 operator (SpMV, sweeps, strict parts), the sweep
 adjoints (dot-product identity against the forward sweep), the face-
 coefficient gradient kernel, and the autograd solve (adjoint MG-PCG +
-face gradient) against finite differences and the oracle gradient."""
+face gradient) against finite differences and the oracle gradient, and at
+the benchmark's 128^3 size by its residuals and the face-gradient identity."""
 import numpy as np
 import pytest
 import torch
@@ -230,3 +231,50 @@ def test_solve_gradient_fd_and_oracle(m):
                 gv = t.grad[idx].item()
                 assert abs(fd - gv) <= 1e-5 * max(1.0, abs(fd)), (idx, fd,
                                                                  gv)
+
+
+def _var7_apply_np(u, kx, ky, kz):
+    """(A u)_p = sum over the faces f of p of k_f (u_p - u_q), u = 0 outside:
+    per axis the face differences of the zero-padded field, weighted, then
+    differenced back onto the points (A = D^T K D)."""
+    out = np.zeros_like(u)
+    for ax, k in ((2, kx), (1, ky), (0, kz)):
+        pad = [(0, 0)] * 3
+        pad[ax] = (1, 1)
+        w = k * np.diff(np.pad(u, pad), axis=ax)
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[ax] = slice(0, -1)
+        hi[ax] = slice(1, None)
+        out += w[tuple(lo)] - w[tuple(hi)]
+    return out
+
+
+def test_solve_gradient_full_size_128(m):
+    """The differentiable solve at the size the benchmark times (128^3, seed
+    5, 4 levels, rtol 1e-10).  The oracle cannot run these solves at this
+    size in a test, so the outputs are checked by what holds at any size:
+    A u = f and A lam = u - u_t (lam = dL/df) to the solve tolerance, and
+    sum_f k_f dL/dk_f = -lam.(A u), since dL/dk_f = -(D lam)_f (D u)_f face
+    by face and A = D^T K D."""
+    shape = (128, 128, 128)
+    banner("autograd solve 128^3")
+    pr = inputs.var7_problem(5, shape)
+    kx, ky, kz = (dev(pr[k]).requires_grad_(True) for k in ("kx", "ky",
+                                                            "kz"))
+    f = dev(pr["f"]).requires_grad_(True)
+    ut = dev(pr["u_t"])
+    L, u = _loss(m, kx, ky, kz, f, ut, 4, 1e-10)
+    L.backward()
+    un, lam = host(u.detach()), host(f.grad)
+    k = (pr["kx"], pr["ky"], pr["kz"])
+    g = (host(kx.grad), host(ky.grad), host(kz.grad))
+    Au = _var7_apply_np(un, *k)
+    res_u = np.linalg.norm(Au - pr["f"]) / np.linalg.norm(pr["f"])
+    du = un - pr["u_t"]
+    res_l = (np.linalg.norm(_var7_apply_np(lam, *k) - du) /
+             np.linalg.norm(du))
+    assert res_u <= 2e-10 and res_l <= 2e-10, (res_u, res_l)
+    kg = sum(float(np.sum(kk * gg)) for kk, gg in zip(k, g))
+    scale = sum(float(np.sum(np.abs(kk * gg))) for kk, gg in zip(k, g))
+    assert abs(kg + float(np.dot(lam.ravel(), Au.ravel()))) <= 1e-11 * scale
