@@ -357,6 +357,17 @@ def var7_workload(torch, m, inputs, dev, reps):
     return out
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -449,7 +460,7 @@ def main():
                           "1 (sharding the sweeps over several GPUs, as "
                           "z-slab pipelines, is not built)"}))
         return 2
-    import numpy as np  # noqa: F401
+    import numpy as np
     import torch
 
     import paper_2204_13304_amd as m
@@ -551,7 +562,10 @@ def main():
     if not args.no_cpu:
         try:
             import oracle
-            bh = b.cpu().numpy()
+            # the same right-hand side, built on the host from the seeded
+            # recipe (the oracle takes no input from the GPU path)
+            bh = (oracle.spmv27(np.ones(shape)) +
+                  inputs.rhs_perturbation(3, shape))
             log("cpu oracle: 1 and 2 MG-PCG iterations")
             ta = time.perf_counter()
             oracle.pcg(bh, precond="mg", levels=L, max_iter=1)
@@ -563,8 +577,9 @@ def main():
                    "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
                    "sample": f"one MG-PCG iteration at {n}^3 (difference of "
                              "a 2-iteration and a 1-iteration oracle run, "
-                             f"{per_it:.2f} s per iteration; host has "
-                             f"{os.cpu_count()} CPUs, the oracle uses one)"}
+                             f"{per_it:.2f} s per iteration; host: "
+                             f"{cpu_model()}, {os.cpu_count()} CPUs, the "
+                             "oracle uses one)"}
         except Exception as e:  # reported, not hidden
             cpu = {"error": repr(e)}
 

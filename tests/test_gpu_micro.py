@@ -158,10 +158,10 @@ def test_ilu27_rejects_tall_tiles_and_f32(m, monkeypatch):
     with pytest.raises(RuntimeError):
         m.ilu27_factor(A, ws)
     # a rejected call leaves the workspace usable
-    r = dev(inputs.standard_normal(53, (8, 8, 8)))
+    rh = inputs.standard_normal(53, (8, 8, 8))
     x = dev(np.zeros((8, 8, 8)))
-    m.symgs(A, r, x, "sym", ws)
-    ref = oracle.symgs27(host(r), np.zeros((8, 8, 8)), "sym")
+    m.symgs(A, dev(rh), x, "sym", ws)
+    ref = oracle.symgs27(rh, np.zeros((8, 8, 8)), "sym")
     assert rel_inf(host(x), ref) <= 1e-13
     monkeypatch.setenv("M2S_C27_WAVES", "2")
     A32 = m.const27((8, 8, 8), dtype=torch.float32)
