@@ -76,3 +76,32 @@ def c27_tiles(shape, kt):
             if rows:
                 out.append((ut, vt))
     return out
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # no CPU fallback: without libm2s.so every entry point raises
+    import torch
+
+    import paper_2204_13304_amd as m
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIBPATH", str(tmp_path / "libm2s.so"))
+    with pytest.raises(RuntimeError, match="libm2s.so not found"):
+        L.load()
+    A = m.const27((4, 4, 4))
+    x = torch.zeros((4, 4, 4), dtype=torch.float64)
+    for call in (lambda: m.spmv(A, x), lambda: m.symgs(A, x, x.clone()),
+                 lambda: m.pcg_solve(A, x),
+                 lambda: m.jacobi9(x[0], x[1].clone(), 1)):
+        with pytest.raises(RuntimeError, match="libm2s.so not found"):
+            call()
+
+
+def test_cpu_tensors_are_rejected():
+    # the library takes device memory only; host tensors never reach it
+    import torch
+
+    import paper_2204_13304_amd as m
+    A = m.const27((4, 4, 4))
+    x = torch.zeros((4, 4, 4), dtype=torch.float64)
+    with pytest.raises(ValueError, match="must be on the GPU"):
+        m.spmv(A, x)
