@@ -12,6 +12,11 @@ kx (nz, ny, nx+1), ky (nz, ny+1, nx), kz (nz+1, ny, nx); BLOCK7 blocks are
 modify their inputs; "in-place" sweeps work on a copy that is returned.
 
 Each wrapped routine cites the part of the paper it follows in the C source.
+
+Parity unpinned: var7_coarsen, the VAR7 coarse-face rule (the paper gives no
+coarse operator for variable coefficients; the rule is a reading, pinned
+only by its constant-coefficient case, the symmetry of the coarse operator
+and the convergence of the multigrid built on it).
 """
 from __future__ import annotations
 
