@@ -77,6 +77,8 @@ def _load():
         g("ilu27_factor").argtypes = [i, i, i, R, R, P]
         g("ilu27_solve").argtypes = [i, i, i, R, P, P, P]
         g("penta_lines").argtypes = [i, i, i, i, P, P, P]
+        g("bt_lines").argtypes = [i, i, i, i, P, P, P]
+        g("bt_lines").restype = i
     lib.m2so_pcg.restype = i
     lib.m2so_pcg.argtypes = [i, i, i, i, d, d, C.c_void_p, C.c_void_p,
                              C.c_void_p, i, i, _dp, _dp, i, d, i,
@@ -331,6 +333,23 @@ def penta_lines(coef, r, axis, dtype=np.float64):
     x = np.empty_like(r)
     _fn("penta_lines", dtype)(nx, ny, nz, {"x": 0, "y": 1, "z": 2}[axis], coef,
                               r, x)
+    return x
+
+
+def bt_lines(coef, r, axis, dtype=np.float64):
+    """Solve the 5x5 block-tridiagonal systems along every grid line of
+    `axis` ("x", "y" or "z"); coef has shape (3, nz, ny, nx, 5, 5) = the
+    blocks A (coupling to the previous point), B, C (to the next point);
+    r has shape (nz, ny, nx, 5)."""
+    coef, r = _c(coef, dtype), _c(r, dtype)
+    nz, ny, nx = r.shape[:3]
+    if r.shape[3:] != (5,) or coef.shape != (3, nz, ny, nx, 5, 5):
+        raise ValueError("bt_lines: coef (3, nz, ny, nx, 5, 5), r (nz, ny, nx, 5)")
+    x = np.empty_like(r)
+    st = _fn("bt_lines", dtype)(nx, ny, nz, {"x": 0, "y": 1, "z": 2}[axis],
+                                coef, r, x)
+    if st != 0:
+        raise ValueError("bt_lines: a pivot block is singular")
     return x
 
 

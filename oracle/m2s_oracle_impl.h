@@ -770,6 +770,120 @@ void FN(penta_lines)(int nx, int ny, int nz, int dir, const REAL *coef,
     free(w);
 }
 
+/* Solve M X = Y for a 5x5 matrix M and a 5 x ncol right-hand side Y (both
+ * row-major; Y is overwritten by X, M by its elimination) by Gaussian
+ * elimination with partial pivoting.  Returns 0, or -1 if a pivot is 0. */
+static int FN(solve5)(REAL *M, REAL *Y, int ncol)
+{
+    for (int c = 0; c < 5; ++c) {
+        int piv = c;
+        for (int q = c + 1; q < 5; ++q)
+            if (fabs((double)M[q * 5 + c]) > fabs((double)M[piv * 5 + c]))
+                piv = q;
+        if (M[piv * 5 + c] == 0) return -1;
+        if (piv != c) {
+            for (int k = 0; k < 5; ++k) {
+                const REAL t = M[c * 5 + k];
+                M[c * 5 + k] = M[piv * 5 + k];
+                M[piv * 5 + k] = t;
+            }
+            for (int k = 0; k < ncol; ++k) {
+                const REAL t = Y[c * ncol + k];
+                Y[c * ncol + k] = Y[piv * ncol + k];
+                Y[piv * ncol + k] = t;
+            }
+        }
+        for (int q = c + 1; q < 5; ++q) {
+            const REAL f = M[q * 5 + c] / M[c * 5 + c];
+            for (int k = c; k < 5; ++k) M[q * 5 + k] -= f * M[c * 5 + k];
+            for (int k = 0; k < ncol; ++k) Y[q * ncol + k] -= f * Y[c * ncol + k];
+        }
+    }
+    for (int c = 4; c >= 0; --c)
+        for (int k = 0; k < ncol; ++k) {
+            REAL v = Y[c * ncol + k];
+            for (int q = c + 1; q < 5; ++q) v -= M[c * 5 + q] * Y[q * ncol + k];
+            Y[c * ncol + k] = v / M[c * 5 + c];
+        }
+    return 0;
+}
+
+/* Block-tridiagonal line solves (the 5x5 block systems of the ADI-shaped
+ * NPB BT solver, Sec. 7.1): along axis `dir` (0 x, 1 y, 2 z) every grid
+ * line holds the system
+ *   A_i x_{i-1} + B_i x_i + C_i x_{i+1} = r_i
+ * in 5-vectors x_i, r_i and 5x5 blocks (i the position on the line; terms
+ * reaching off the line are absent).  coef = [3][nz][ny][nx][5][5] holds
+ * A, B, C at every point (row-major blocks); r, x = [nz][ny][nx][5].
+ * Block Gaussian elimination down the line, then back substitution (the
+ * block Thomas algorithm): with G_{-1} = 0 and y_{-1} = 0,
+ *   M_i = B_i - A_i G_{i-1},  G_i = M_i^{-1} C_i,
+ *   y_i = M_i^{-1} (r_i - A_i y_{i-1});
+ *   x_{L-1} = y_{L-1},  x_i = y_i - G_i x_{i+1}.
+ * Returns 0, or -1 if some M_i is singular. */
+int FN(bt_lines)(int nx, int ny, int nz, int dir, const REAL *coef,
+                 const REAL *r, REAL *x)
+{
+    const long n = (long)nx * ny * nz;
+    const int len = dir == 0 ? nx : dir == 1 ? ny : nz;
+    const long stride = dir == 0 ? 1 : dir == 1 ? nx : (long)nx * ny;
+    REAL *G = (REAL *)malloc(sizeof(REAL) * 25 * (size_t)len);
+    REAL *Yv = (REAL *)malloc(sizeof(REAL) * 5 * (size_t)len);
+    int status = 0;
+    for (long base = 0; base < n && status == 0; ++base) {
+        const int i0 = (int)(base % nx), j0 = (int)((base / nx) % ny),
+                  k0 = (int)(base / ((long)nx * ny));
+        if ((dir == 0 && i0) || (dir == 1 && j0) || (dir == 2 && k0))
+            continue;  /* base is the first point of its line */
+        for (int i = 0; i < len; ++i) {
+            const long p = base + i * stride;
+            const REAL *A = coef + 25 * p;
+            const REAL *B = coef + 25 * (n + p);
+            const REAL *Cb = coef + 25 * (2 * n + p);
+            /* the augmented system [M | C_i  r_i - A_i y_{i-1}] */
+            REAL M[25], Y[30];
+            for (int a = 0; a < 5; ++a) {
+                for (int b = 0; b < 5; ++b) {
+                    REAL m = B[a * 5 + b];
+                    if (i > 0)
+                        for (int c = 0; c < 5; ++c)
+                            m -= A[a * 5 + c] * G[25 * (i - 1) + c * 5 + b];
+                    M[a * 5 + b] = m;
+                    Y[a * 6 + b] = Cb[a * 5 + b];
+                }
+                REAL v = r[5 * p + a];
+                if (i > 0)
+                    for (int c = 0; c < 5; ++c)
+                        v -= A[a * 5 + c] * Yv[5 * (i - 1) + c];
+                Y[a * 6 + 5] = v;
+            }
+            if (FN(solve5)(M, Y, 6)) {
+                status = -1;
+                break;
+            }
+            for (int a = 0; a < 5; ++a) {
+                for (int b = 0; b < 5; ++b) G[25 * i + a * 5 + b] = Y[a * 6 + b];
+                Yv[5 * i + a] = Y[a * 6 + 5];
+            }
+        }
+        if (status) break;
+        for (int i = len - 1; i >= 0; --i) {
+            const long p = base + i * stride;
+            for (int a = 0; a < 5; ++a) {
+                REAL v = Yv[5 * i + a];
+                if (i + 1 < len)
+                    for (int c = 0; c < 5; ++c)
+                        v -= G[25 * i + a * 5 + c] *
+                             x[5 * (base + (i + 1) * stride) + c];
+                x[5 * p + a] = v;
+            }
+        }
+    }
+    free(G);
+    free(Yv);
+    return status;
+}
+
 #undef KX
 #undef KY
 #undef KZ

@@ -58,6 +58,18 @@ def block7_blocks(seed=4, dominance=10.0):
     return np.ascontiguousarray(b)
 
 
+def bt_problem(seed, shape, dominance=20.0):
+    """Blocks and right-hand side of 5x5 block-tridiagonal line systems on a
+    grid of shape (nz, ny, nx): per point the blocks A, B, C with entries
+    U(-1, 1), shape (3, nz, ny, nx, 5, 5), B getting +dominance on its
+    diagonal; r ~ N(0, 1) of shape (nz, ny, nx, 5)."""
+    rng = np.random.default_rng(seed)
+    coef = rng.uniform(-1.0, 1.0, size=(3,) + tuple(shape) + (5, 5))
+    coef[1] += dominance * np.eye(5)
+    r = rng.standard_normal(tuple(shape) + (5,))
+    return np.ascontiguousarray(coef), r
+
+
 def var7_problem(seed, shape, log_std=0.5):
     """Face coefficients and data for the variable-coefficient diffusion
     problem on a grid of shape (nz, ny, nx)."""

@@ -1,6 +1,7 @@
 """Pins of the oracle's microbenchmark routines (Sec. 7.2.1: Jacobi
 iterations of a 2-D 9-point stencil, the 27-point ILU) and of its
-pentadiagonal line solves (the SP-shaped systems of Sec. 7.1), against
+pentadiagonal and 5x5 block-tridiagonal line solves (the SP- and
+BT-shaped systems of Sec. 7.1), against
 closed forms, fixed points, defining properties and library routines
 (scipy.sparse, scipy.linalg.solve_banded) -- never against a retyping of
 the oracle's own loops."""
@@ -151,3 +152,70 @@ def test_penta_lines_residual():
     res[..., :-1] += d[..., :-1] * x[..., 1:]
     res[..., :-2] += e[..., :-2] * x[..., 2:]
     assert np.max(np.abs(res - r)) <= 1e-13
+
+
+# ------------------------------------------ block-tridiagonal (5x5) lines
+def _bt_matrix(coef, axis):
+    """The block-tridiagonal operator of every line of `axis` as one sparse
+    matrix over the grid's 5-vectors (C order of (nz, ny, nx, 5))."""
+    nz, ny, nx = coef.shape[1:4]
+    ax = {"x": 2, "y": 1, "z": 0}[axis]
+    length = (nz, ny, nx)[ax]
+    step = (nx * ny, nx, 1)[ax]
+    idx = np.arange(nx * ny * nz).reshape(nz, ny, nx)
+    pos = np.indices((nz, ny, nx))[ax]
+    rows, cols, vals = [], [], []
+    for blk, off in ((0, -1), (1, 0), (2, 1)):
+        ok = (pos + off >= 0) & (pos + off < length)
+        p = idx[ok]
+        q = p + off * step
+        v = coef[blk][ok]  # (m, 5, 5)
+        for a in range(5):
+            for b in range(5):
+                rows.append(5 * p + a)
+                cols.append(5 * q + b)
+                vals.append(v[:, a, b])
+    n5 = 5 * nx * ny * nz
+    return sp.csr_matrix((np.concatenate(vals),
+                          (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(n5, n5))
+
+
+@pytest.mark.parametrize("axis", ["x", "y", "z"])
+@pytest.mark.parametrize("shape", [(3, 4, 5), (1, 1, 7), (6, 1, 1),
+                                   (2, 5, 3)])
+def test_bt_lines_against_spsolve(axis, shape):
+    from paper_2204_13304_amd import inputs
+    coef, r = inputs.bt_problem(60, shape)
+    x = oracle.bt_lines(coef, r, axis)
+    ref = spla.spsolve(_bt_matrix(coef, axis).tocsc(), r.ravel())
+    assert np.max(np.abs(x.ravel() - ref)) <= 1e-13 * np.abs(ref).max()
+
+
+def test_bt_lines_uncoupled_is_pointwise_solve():
+    # with A = C = 0 every point is its own 5x5 system B_p x_p = r_p
+    from paper_2204_13304_amd import inputs
+    coef, r = inputs.bt_problem(61, (3, 4, 6))
+    coef[0] = 0.0
+    coef[2] = 0.0
+    ref = np.linalg.solve(coef[1], r[..., None])[..., 0]
+    for axis in ("x", "y", "z"):
+        x = oracle.bt_lines(coef, r, axis)
+        assert np.max(np.abs(x - ref)) <= 1e-14 * np.abs(ref).max()
+
+
+def test_bt_lines_residual_and_singular_pivot():
+    from paper_2204_13304_amd import inputs
+    coef, r = inputs.bt_problem(62, (2, 3, 9))
+    x = oracle.bt_lines(coef, r, "x")
+    A, B, C = coef
+    res = np.einsum("...ab,...b->...a", B, x)
+    res[..., 1:, :] += np.einsum("...ab,...b->...a", A[..., 1:, :, :],
+                                 x[..., :-1, :])
+    res[..., :-1, :] += np.einsum("...ab,...b->...a", C[..., :-1, :, :],
+                                  x[..., 1:, :])
+    assert np.max(np.abs(res - r)) <= 1e-13 * np.abs(r).max()
+    coef[1, 0, 0, 0] = 0.0  # a zero first pivot block: reported, not hidden
+    coef[0, 0, 0, 0] = 0.0
+    with pytest.raises(ValueError, match="singular"):
+        oracle.bt_lines(coef, r, "x")
