@@ -96,8 +96,8 @@ def parse():
     ap.add_argument("--workloads-only", action="store_true",
                     help="only the workloads beside the 27-point sweep")
     ap.add_argument("--workloads",
-                    default="ssor,var7,jacobi,penta,ilu,xline,probe512",
-                    help="which of them: ssor, var7, jacobi, penta, ilu, "
+                    default="ssor,var7,jacobi,penta,bt,ilu,xline,probe512",
+                    help="which of them: ssor, var7, jacobi, penta, bt, ilu, "
                          "xline, probe512 (comma-separated)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the kernel loops and a copy calibration")
@@ -124,7 +124,7 @@ def flops_per_iteration(n, levels):
 
 
 def extra_workloads(torch, m, inputs, dev, reps,
-                    which=("ssor", "var7", "jacobi", "penta", "ilu",
+                    which=("ssor", "var7", "jacobi", "penta", "bt", "ilu",
                            "xline", "probe512")):
     """The workloads beside the 27-point sweep, by name."""
     out = {}
@@ -136,6 +136,8 @@ def extra_workloads(torch, m, inputs, dev, reps,
         out.update(jacobi_workload(torch, m, inputs, dev, reps))
     if "penta" in which:
         out.update(penta_workload(torch, m, inputs, dev, reps))
+    if "bt" in which:
+        out.update(bt_workload(torch, m, inputs, dev, reps))
     if "ilu" in which:
         out.update(ilu_workload(torch, m, inputs, dev, reps))
     if "xline" in which:
@@ -248,6 +250,38 @@ def penta_workload(torch, m, inputs, dev, reps):
         "ms": res, "achieved": gbs,
         "unit": "GB/s (104 B per point: read 5 bands and r, write and "
                 "reread the normalised row, write x)",
+        "frac": {a: g / HBM_PEAK_GBS for a, g in gbs.items()}}}
+
+
+def bt_workload(torch, m, inputs, dev, reps):
+    """5x5 block-tridiagonal line solves along x, y and z at 162^3
+    (BT-shaped, synthetic blocks with a dominant diagonal block)."""
+    n = 162
+    shape = (n, n, n)
+    coef_h, r_h = inputs.bt_problem(70, shape)
+    coef = torch.from_numpy(coef_h).to(dev)
+    r = torch.from_numpy(r_h).to(dev)
+    del coef_h, r_h
+    x = torch.empty_like(r)
+    work = torch.empty(shape + (5, 5), dtype=torch.float64, device=dev)
+    res = {}
+    for axis in ("x", "y", "z"):
+        m.bt_lines(coef, r, axis, x, work)
+        res[axis] = event_ms(
+            torch, lambda: m.bt_lines(coef, r, axis, x, work), reps)
+    # per point: read A, B, C (600 B) and r (40 B); write G (200 B) and y
+    # (40 B); read both back (240 B); write x (40 B)
+    bpp = 1160
+    gbs = {a: bpp * n ** 3 / (t * 1e-3) / 1e9 for a, t in res.items()}
+    log("bt lines 162^3: " + ", ".join(
+        f"{a} {res[a]:.3f} ms ({gbs[a]:.0f} GB/s)" for a in res))
+    return {"bt_lines": {
+        "workload": "5x5 block-tridiagonal systems along every x, y, z line "
+                    "of 162^3, FP64, blocks U(-1,1) (+20 I on the diagonal "
+                    "block) seed 70",
+        "ms": res, "achieved": gbs,
+        "unit": f"GB/s ({bpp} B per point: read the three blocks and r, "
+                "write and reread G and y, write x)",
         "frac": {a: g / HBM_PEAK_GBS for a, g in gbs.items()}}}
 
 

@@ -360,6 +360,30 @@ m2s_status m2s_penta_lines(int32_t nx, int32_t ny, int32_t nz, int32_t axis,
                            double *work, hipStream_t stream);
 
 /* ---------------------------------------------------------------------
+ * 5x5 block-tridiagonal line solves (the block systems of the ADI-shaped
+ * NPB BT solver, Sec. 7.1): along axis 0 (x), 1 (y) or 2 (z) every grid
+ * line of an nx x ny x nz grid holds
+ *   A_i x_{i-1} + B_i x_i + C_i x_{i+1} = r_i
+ * in 5-vectors x_i, r_i with 5x5 blocks (i the position on the line; the
+ * first point's A and the last point's C couple to nothing and are not
+ * read).  coef: device, F64, [3][nz][ny][nx][5][5] = A, B, C at every
+ * point, blocks row-major (75 n doubles); r: [nz][ny][nx][5] (5 n
+ * doubles); x: the solution, same layout (overwritten); work: 25 n doubles
+ * of caller-owned scratch (overwritten).  Block Gaussian elimination down
+ * each line (G_i = M_i^{-1} C_i, y_i = M_i^{-1}(r_i - A_i y_{i-1}),
+ * M_i = B_i - A_i G_{i-1}) and back substitution x_i = y_i - G_i x_{i+1},
+ * one line per GPU lane, both passes in one launch.  The pivot blocks M_i
+ * are factored without pivoting: the systems must keep them safely
+ * nonsingular (e.g. block diagonal dominance); a zero pivot gives
+ * non-finite values, not an error.  None of the four buffers may overlap
+ * (M2S_ERR_ALIAS); n = nx*ny*nz < 2^31 (M2S_ERR_SHAPE); null pointers or an
+ * axis outside 0..2 give M2S_ERR_ARG.
+ * --------------------------------------------------------------------- */
+m2s_status m2s_bt_lines(int32_t nx, int32_t ny, int32_t nz, int32_t axis,
+                        const double *coef, const double *r, double *x,
+                        double *work, hipStream_t stream);
+
+/* ---------------------------------------------------------------------
  * Schedule of the wavefront sweep (host only, no GPU needed), exposed so
  * the schedule's legality (every dependence from a strictly earlier step)
  * can be checked on the CPU.  Point (i, j, k) runs at step

@@ -88,6 +88,8 @@ _SIGS = {
                               _P, _P, _P, C.c_int32, C.c_int32, _P]),
     "m2s_penta_lines": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                   _P, _P, _P, _P, _P]),
+    "m2s_bt_lines": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                               _P, _P, _P, _P, _P]),
     "m2s_ilu27_factor": (C.c_int, [_S, _P, _P, _P]),
     "m2s_ilu27_apply": (C.c_int, [_S, _P, _P, _P, _P, _P]),
     "m2s_dot": (C.c_int, [_P, _P, C.c_int64, _P, _P]),

@@ -371,6 +371,29 @@ def penta_lines(coef, r, axis, x=None, work=None):
     return x
 
 
+def bt_lines(coef, r, axis, x=None, work=None):
+    """Solve the 5x5 block-tridiagonal systems along every grid line of
+    `axis` ("x", "y" or "z"); coef (3, nz, ny, nx, 5, 5) holds the blocks
+    A, B, C of every point, r and x are (nz, ny, nx, 5)."""
+    lib = L.load()
+    if r.dim() != 4 or r.shape[3] != 5:
+        raise ValueError("bt_lines takes fields of shape (nz, ny, nx, 5)")
+    nz, ny, nx = r.shape[:3]
+    _need(r, torch.float64, (nz, ny, nx, 5), "r")
+    _need(coef, torch.float64, (3, nz, ny, nx, 5, 5), "coef")
+    if x is None:
+        x = torch.empty_like(r)
+    if work is None:
+        work = torch.empty((nz, ny, nx, 5, 5), dtype=torch.float64,
+                           device=r.device)
+    _need(x, torch.float64, (nz, ny, nx, 5), "x")
+    _need(work, torch.float64, (nz, ny, nx, 5, 5), "work")
+    L.check(lib.m2s_bt_lines(nx, ny, nz, {"x": 0, "y": 1, "z": 2}[axis],
+                             _ptr(coef), _ptr(r), _ptr(x), _ptr(work),
+                             _stream()), "m2s_bt_lines")
+    return x
+
+
 def face_grad(A: Stencil, u, lam):
     lib = L.load()
     nz, ny, nx = A.shape

@@ -739,6 +739,23 @@ m2s_status m2s_penta_lines(int32_t nx, int32_t ny, int32_t nz, int32_t axis,
         launch_penta_lines(nx, ny, nz, axis, coef, r, x, work, stream));
 }
 
+m2s_status m2s_bt_lines(int32_t nx, int32_t ny, int32_t nz, int32_t axis,
+                        const double *coef, const double *r, double *x,
+                        double *work, hipStream_t stream)
+{
+    if (!coef || !r || !x || !work || axis < 0 || axis > 2) return M2S_ERR_ARG;
+    if (nx < 1 || ny < 1 || nz < 1 ||
+        (int64_t)nx * ny * nz >= ((int64_t)1 << 31))
+        return M2S_ERR_SHAPE;
+    const size_t pb = sizeof(double) * (size_t)nx * ny * nz;  // per scalar
+    if (overlap2(coef, 75 * pb, r, 5 * pb) || overlap2(coef, 75 * pb, x, 5 * pb) ||
+        overlap2(coef, 75 * pb, work, 25 * pb) || overlap(r, x, 5 * pb) ||
+        overlap2(r, 5 * pb, work, 25 * pb) || overlap2(x, 5 * pb, work, 25 * pb))
+        return M2S_ERR_ALIAS;
+    return hip_status(
+        launch_bt_lines(nx, ny, nz, axis, coef, r, x, work, stream));
+}
+
 m2s_status m2s_jacobi9(int32_t nx, int32_t ny, double diag, double off,
                        const double *b, double *x, double *tmp, int32_t iters,
                        int32_t tblock, hipStream_t stream)

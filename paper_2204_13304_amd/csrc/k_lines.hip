@@ -1,5 +1,6 @@
-// k_lines.hip -- batched pentadiagonal line solves (the scalar multi-
-// diagonal systems of the ADI-shaped NPB SP solver, Sec. 7.1) for gfx950.
+// k_lines.hip -- batched line solves for gfx950: pentadiagonal (the scalar
+// multi-diagonal systems of the ADI-shaped NPB SP solver, Sec. 7.1) and
+// 5x5 block-tridiagonal (those of NPB BT; at the end of the file).
 //
 // Along axis x, y or z every grid line holds the system
 //   a_i x_{i-2} + b_i x_{i-1} + c_i x_i + d_i x_{i+1} + e_i x_{i+2} = r_i.
@@ -255,6 +256,159 @@ hipError_t launch_penta_lines(int nx, int ny, int nz, int axis,
     if (split == 4)
         return penta_launch<4>(nx, ny, nz, axis, coef, r, x, work, s);
     return penta_launch<2>(nx, ny, nz, axis, coef, r, x, work, s);
+}
+
+// ------------------------------------------------------------------------
+// 5x5 block-tridiagonal line solves (the block systems of the ADI-shaped NPB
+// BT solver, Sec. 7.1).  Along the axis every line holds
+//   A_i x_{i-1} + B_i x_i + C_i x_{i+1} = r_i
+// in 5-vectors; coef = [3][n][5][5] (A, B, C per point, row-major), r and x
+// = [n][5].  Block elimination down the line keeps G_i = M_i^{-1} C_i and
+// y_i = M_i^{-1} (r_i - A_i y_{i-1}) with M_i = B_i - A_i G_{i-1}, then back
+// substitution x_i = y_i - G_i x_{i+1}: G goes to the work buffer
+// (25 doubles per point), y into x.  One lane per line holds G_{i-1},
+// y_{i-1}, the pivot block and its LU in registers; elimination and back
+// substitution run in one launch.  The pivot blocks are factored without
+// pivoting (the systems must keep them safely nonsingular, e.g. block
+// diagonal dominance).
+constexpr int BT_NT = 64;
+
+// in-place LU of a 5x5 block without pivoting: unit lower factor below the
+// diagonal (the multipliers), upper factor on and above it
+__device__ __forceinline__ void bt_lu5(double (&m)[25])
+{
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+#pragma unroll
+        for (int q = c + 1; q < 5; ++q) {
+            const double f = m[q * 5 + c] / m[c * 5 + c];
+            m[q * 5 + c] = f;
+#pragma unroll
+            for (int k = c + 1; k < 5; ++k) m[q * 5 + k] -= f * m[c * 5 + k];
+        }
+    }
+}
+
+// v <- M^{-1} v with M's LU from bt_lu5
+__device__ __forceinline__ void bt_lu5_solve(const double (&m)[25],
+                                             double (&v)[5])
+{
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+#pragma unroll
+        for (int q = c + 1; q < 5; ++q) v[q] -= m[q * 5 + c] * v[c];
+#pragma unroll
+    for (int c = 4; c >= 0; --c) {
+#pragma unroll
+        for (int q = c + 1; q < 5; ++q) v[c] -= m[c * 5 + q] * v[q];
+        v[c] = v[c] / m[c * 5 + c];
+    }
+}
+
+template <int AXIS>
+__global__ void __launch_bounds__(BT_NT)
+    bt_lines_kernel(int nx, int ny, int nz, const double *__restrict__ coef,
+                    const double *__restrict__ r, double *__restrict__ x,
+                    double *__restrict__ work)
+{
+    const LineMap<AXIS> M{nx, ny, nz};
+    const int line = blockIdx.x * BT_NT + threadIdx.x;
+    if (line >= M.nlines()) return;
+    const long n = (long)nx * ny * nz;
+    const int len = M.len();
+    const long st = M.stride(), base = M.base(line);
+
+    // ---- elimination down the line
+    double g[25], y[5];  // G_{i-1}, y_{i-1}
+    for (int i = 0; i < len; ++i) {
+        const long p = base + (long)i * st;
+        const double *Ab = coef + 25 * p;
+        const double *Bb = coef + 25 * (n + p);
+        const double *Cb = coef + 25 * (2 * n + p);
+        double m[25], v[5];
+#pragma unroll
+        for (int e = 0; e < 25; ++e) m[e] = Bb[e];
+#pragma unroll
+        for (int a = 0; a < 5; ++a) v[a] = r[5 * p + a];
+        if (i > 0) {
+            // M = B - A G_{i-1}, v = r - A y_{i-1} (the first point's A
+            // couples to nothing and is not read)
+            double ab[25];
+#pragma unroll
+            for (int e = 0; e < 25; ++e) ab[e] = Ab[e];
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+#pragma unroll
+                for (int b = 0; b < 5; ++b)
+#pragma unroll
+                    for (int c = 0; c < 5; ++c)
+                        m[a * 5 + b] -= ab[a * 5 + c] * g[c * 5 + b];
+#pragma unroll
+                for (int c = 0; c < 5; ++c) v[a] -= ab[a * 5 + c] * y[c];
+            }
+        }
+        bt_lu5(m);
+        if (i + 1 < len) {
+            // G_i = M^{-1} C_i column by column (the last point's C is not
+            // read: nothing follows it)
+#pragma unroll
+            for (int b = 0; b < 5; ++b) {
+                double col[5];
+#pragma unroll
+                for (int a = 0; a < 5; ++a) col[a] = Cb[a * 5 + b];
+                bt_lu5_solve(m, col);
+#pragma unroll
+                for (int a = 0; a < 5; ++a) g[a * 5 + b] = col[a];
+            }
+#pragma unroll
+            for (int e = 0; e < 25; ++e) work[25 * p + e] = g[e];
+        }
+        bt_lu5_solve(m, v);
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            y[a] = v[a];
+            x[5 * p + a] = v[a];
+        }
+    }
+
+    // ---- back substitution: x_{L-1} = y_{L-1} is in place already
+    double xn[5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) xn[a] = y[a];
+    for (int i = len - 2; i >= 0; --i) {
+        const long p = base + (long)i * st;
+        double gi[25], xi[5];
+#pragma unroll
+        for (int e = 0; e < 25; ++e) gi[e] = work[25 * p + e];
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            double v = x[5 * p + a];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) v -= gi[a * 5 + c] * xn[c];
+            xi[a] = v;
+        }
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            x[5 * p + a] = xi[a];
+            xn[a] = xi[a];
+        }
+    }
+}
+
+hipError_t launch_bt_lines(int nx, int ny, int nz, int axis,
+                           const double *coef, const double *r, double *x,
+                           double *work, hipStream_t s)
+{
+    const long nlines = axis == 0   ? (long)ny * nz
+                        : axis == 1 ? (long)nx * nz
+                                    : (long)nx * ny;
+    const int grid = (int)((nlines + BT_NT - 1) / BT_NT);
+    auto k = axis == 0   ? bt_lines_kernel<0>
+             : axis == 1 ? bt_lines_kernel<1>
+                         : bt_lines_kernel<2>;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(BT_NT), 0, s, nx, ny, nz, coef, r,
+                       x, work);
+    return hipGetLastError();
 }
 
 }  // namespace m2s

@@ -322,6 +322,9 @@ hipError_t launch_jacobi9(int nx, int ny, double diag, double off,
 hipError_t launch_penta_lines(int nx, int ny, int nz, int axis,
                               const double *coef, const double *r, double *x,
                               double *work, hipStream_t s);
+hipError_t launch_bt_lines(int nx, int ny, int nz, int axis,
+                           const double *coef, const double *r, double *x,
+                           double *work, hipStream_t s);
 
 // bytes of one boundary record: the value and the launch epoch
 inline size_t c27_record_bytes(m2s_dtype t) { return t == M2S_F64 ? 16 : 8; }

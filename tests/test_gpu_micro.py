@@ -1,6 +1,7 @@
 """GPU parity of the microbenchmark kernels (Sec. 7.2.1: Jacobi iterations
 of the 2-D 9-point operator, temporally blocked) and of the pentadiagonal
-line solves (Sec. 7.1, SP-shaped), against the oracle."""
+and 5x5 block-tridiagonal line solves (Sec. 7.1, SP- and BT-shaped),
+against the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -120,6 +121,41 @@ def test_penta_lines_rejects_aliasing(m):
     r = torch.zeros((4, 4, 4), dtype=torch.float64, device="cuda")
     with pytest.raises(RuntimeError):
         m.penta_lines(coef, r, "x", x=coef[0])
+
+
+@pytest.mark.parametrize("axis", ["x", "y", "z"])
+@pytest.mark.parametrize("shape", [(5, 7, 9), (1, 1, 1), (1, 1, 70),
+                                   (70, 1, 1), (3, 65, 2), (2, 3, 130)])
+def test_bt_lines_parity(m, axis, shape):
+    banner(f"bt lines {axis} {shape}")
+    coef, r = inputs.bt_problem(63, shape)
+    x = m.bt_lines(dev(coef), dev(r), axis)
+    assert rel_inf(host(x), oracle.bt_lines(coef, r, axis)) <= 1e-13
+
+
+def test_bt_lines_full_size_162(m):
+    # the BT-shaped workload the benchmark times: every line of 162^3 along
+    # each axis against the oracle
+    shape = (162, 162, 162)
+    banner("bt lines 162^3")
+    coef, r = inputs.bt_problem(70, shape)
+    cg, rg = dev(coef), dev(r)
+    work = torch.empty(shape + (5, 5), dtype=torch.float64, device="cuda")
+    for axis in ("x", "y", "z"):
+        x = m.bt_lines(cg, rg, axis, work=work)
+        assert rel_inf(host(x), oracle.bt_lines(coef, r, axis)) <= 1e-13
+
+
+def test_bt_lines_rejects_bad_arguments(m):
+    coef = torch.zeros((3, 4, 4, 4, 5, 5), dtype=torch.float64,
+                       device="cuda")
+    r = torch.zeros((4, 4, 4, 5), dtype=torch.float64, device="cuda")
+    with pytest.raises(RuntimeError, match="M2S_ERR_ALIAS"):
+        m.bt_lines(coef, r, "x", x=r)
+    with pytest.raises(ValueError):
+        m.bt_lines(coef[:, :3], r, "x")
+    with pytest.raises(KeyError):
+        m.bt_lines(coef, r, "w")
 
 
 @pytest.mark.parametrize("shape", [(9, 7, 6), (16, 16, 16), (13, 26, 9),
