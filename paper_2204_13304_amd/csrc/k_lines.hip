@@ -318,24 +318,43 @@ __global__ void __launch_bounds__(BT_NT)
     const int len = M.len();
     const long st = M.stride(), base = M.base(line);
 
-    // ---- elimination down the line
+    // ---- elimination down the line.  The next point's blocks and r are
+    // loaded into registers while the current point is eliminated, so each
+    // lane keeps a point's worth of loads in flight behind its arithmetic.
+    double na[25], nb[25], nc[25], nr[5];
+    auto fetch = [&](int i) {
+        const long p = base + (long)i * st;
+        // the first point's A and the last point's C couple to nothing and
+        // are not read
+        if (i > 0) {
+#pragma unroll
+            for (int e = 0; e < 25; ++e) na[e] = coef[25 * p + e];
+        }
+#pragma unroll
+        for (int e = 0; e < 25; ++e) nb[e] = coef[25 * (n + p) + e];
+        if (i + 1 < len) {
+#pragma unroll
+            for (int e = 0; e < 25; ++e) nc[e] = coef[25 * (2 * n + p) + e];
+        }
+#pragma unroll
+        for (int a = 0; a < 5; ++a) nr[a] = r[5 * p + a];
+    };
     double g[25], y[5];  // G_{i-1}, y_{i-1}
+    fetch(0);
     for (int i = 0; i < len; ++i) {
         const long p = base + (long)i * st;
-        const double *Ab = coef + 25 * p;
-        const double *Bb = coef + 25 * (n + p);
-        const double *Cb = coef + 25 * (2 * n + p);
-        double m[25], v[5];
+        double ab[25], m[25], cb[25], v[5];
 #pragma unroll
-        for (int e = 0; e < 25; ++e) m[e] = Bb[e];
+        for (int e = 0; e < 25; ++e) {
+            ab[e] = na[e];
+            m[e] = nb[e];
+            cb[e] = nc[e];
+        }
 #pragma unroll
-        for (int a = 0; a < 5; ++a) v[a] = r[5 * p + a];
+        for (int a = 0; a < 5; ++a) v[a] = nr[a];
+        if (i + 1 < len) fetch(i + 1);
         if (i > 0) {
-            // M = B - A G_{i-1}, v = r - A y_{i-1} (the first point's A
-            // couples to nothing and is not read)
-            double ab[25];
-#pragma unroll
-            for (int e = 0; e < 25; ++e) ab[e] = Ab[e];
+            // M = B - A G_{i-1}, v = r - A y_{i-1}
 #pragma unroll
             for (int a = 0; a < 5; ++a) {
 #pragma unroll
@@ -349,13 +368,12 @@ __global__ void __launch_bounds__(BT_NT)
         }
         bt_lu5(m);
         if (i + 1 < len) {
-            // G_i = M^{-1} C_i column by column (the last point's C is not
-            // read: nothing follows it)
+            // G_i = M^{-1} C_i column by column
 #pragma unroll
             for (int b = 0; b < 5; ++b) {
                 double col[5];
 #pragma unroll
-                for (int a = 0; a < 5; ++a) col[a] = Cb[a * 5 + b];
+                for (int a = 0; a < 5; ++a) col[a] = cb[a * 5 + b];
                 bt_lu5_solve(m, col);
 #pragma unroll
                 for (int a = 0; a < 5; ++a) g[a * 5 + b] = col[a];
@@ -371,18 +389,31 @@ __global__ void __launch_bounds__(BT_NT)
         }
     }
 
-    // ---- back substitution: x_{L-1} = y_{L-1} is in place already
+    // ---- back substitution: x_{L-1} = y_{L-1} is in place already; the
+    // next (lower) point's G and y are loaded while the current one is done
     double xn[5];
 #pragma unroll
     for (int a = 0; a < 5; ++a) xn[a] = y[a];
+    double ng[25], ny5[5];
+    auto fetch_back = [&](int i) {
+        const long p = base + (long)i * st;
+#pragma unroll
+        for (int e = 0; e < 25; ++e) ng[e] = work[25 * p + e];
+#pragma unroll
+        for (int a = 0; a < 5; ++a) ny5[a] = x[5 * p + a];
+    };
+    if (len >= 2) fetch_back(len - 2);
     for (int i = len - 2; i >= 0; --i) {
         const long p = base + (long)i * st;
-        double gi[25], xi[5];
+        double gi[25], yi[5], xi[5];
 #pragma unroll
-        for (int e = 0; e < 25; ++e) gi[e] = work[25 * p + e];
+        for (int e = 0; e < 25; ++e) gi[e] = ng[e];
+#pragma unroll
+        for (int a = 0; a < 5; ++a) yi[a] = ny5[a];
+        if (i > 0) fetch_back(i - 1);
 #pragma unroll
         for (int a = 0; a < 5; ++a) {
-            double v = x[5 * p + a];
+            double v = yi[a];
 #pragma unroll
             for (int c = 0; c < 5; ++c) v -= gi[a * 5 + c] * xn[c];
             xi[a] = v;
