@@ -29,8 +29,9 @@ Also reported on the same line:
                     per half-sweep); the differentiable VAR7 solve at
                     128^3 (MG-PCG to 1e-10, then the adjoint solve and the
                     face gradient of 0.5*|u - u_t|^2); temporally blocked
-                    Jacobi (4096^2, 64 iterations); pentadiagonal line
-                    solves (162^3, x, y, z); the 27-point ILU (256^3);
+                    Jacobi (4096^2, 64 iterations); pentadiagonal and
+                    5x5 block-tridiagonal line solves (162^3, x, y, z);
+                    the 27-point ILU (256^3);
                     the x-line scan variant of the 27-point sweep (256^3);
                     the 27-point sweep and SpMV at 512^3 (beyond the MALL).
 
