@@ -349,10 +349,20 @@ def ilu27_apply(A: Stencil, w, r, z=None, ws: Workspace | None = None):
     return z
 
 
+_AXES = {"x": 0, "y": 1, "z": 2}
+
+
+def _axis(axis):
+    if axis not in _AXES:
+        raise ValueError(f"axis must be 'x', 'y' or 'z', got {axis!r}")
+    return _AXES[axis]
+
+
 def penta_lines(coef, r, axis, x=None, work=None):
     """Solve the pentadiagonal systems along every grid line of `axis`
     ("x", "y" or "z"); coef (5, nz, ny, nx) holds the bands a..e."""
     lib = L.load()
+    ax = _axis(axis)
     if r.dim() != 3:
         raise ValueError("penta_lines takes 3-D fields (nz, ny, nx)")
     nz, ny, nx = r.shape
@@ -365,7 +375,7 @@ def penta_lines(coef, r, axis, x=None, work=None):
                            device=r.device)
     _need(x, torch.float64, (nz, ny, nx), "x")
     _need(work, torch.float64, (2, nz, ny, nx), "work")
-    L.check(lib.m2s_penta_lines(nx, ny, nz, {"x": 0, "y": 1, "z": 2}[axis],
+    L.check(lib.m2s_penta_lines(nx, ny, nz, ax,
                                 _ptr(coef), _ptr(r), _ptr(x), _ptr(work),
                                 _stream()), "m2s_penta_lines")
     return x
@@ -376,6 +386,7 @@ def bt_lines(coef, r, axis, x=None, work=None):
     `axis` ("x", "y" or "z"); coef (3, nz, ny, nx, 5, 5) holds the blocks
     A, B, C of every point, r and x are (nz, ny, nx, 5)."""
     lib = L.load()
+    ax = _axis(axis)
     if r.dim() != 4 or r.shape[3] != 5:
         raise ValueError("bt_lines takes fields of shape (nz, ny, nx, 5)")
     nz, ny, nx = r.shape[:3]
@@ -388,7 +399,7 @@ def bt_lines(coef, r, axis, x=None, work=None):
                            device=r.device)
     _need(x, torch.float64, (nz, ny, nx, 5), "x")
     _need(work, torch.float64, (nz, ny, nx, 5, 5), "work")
-    L.check(lib.m2s_bt_lines(nx, ny, nz, {"x": 0, "y": 1, "z": 2}[axis],
+    L.check(lib.m2s_bt_lines(nx, ny, nz, ax,
                              _ptr(coef), _ptr(r), _ptr(x), _ptr(work),
                              _stream()), "m2s_bt_lines")
     return x

@@ -105,3 +105,16 @@ def test_cpu_tensors_are_rejected():
     x = torch.zeros((4, 4, 4), dtype=torch.float64)
     with pytest.raises(ValueError, match="must be on the GPU"):
         m.spmv(A, x)
+
+
+def test_line_solves_reject_a_bad_axis():
+    import torch
+
+    import paper_2204_13304_amd as m
+    r = torch.zeros((2, 2, 2, 5), dtype=torch.float64)
+    coef = torch.zeros((3, 2, 2, 2, 5, 5), dtype=torch.float64)
+    with pytest.raises(ValueError, match="axis"):
+        m.bt_lines(coef, r, "w")
+    with pytest.raises(ValueError, match="axis"):
+        m.penta_lines(torch.zeros((5, 2, 2, 2), dtype=torch.float64),
+                      r[..., 0], 3)

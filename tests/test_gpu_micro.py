@@ -154,7 +154,7 @@ def test_bt_lines_rejects_bad_arguments(m):
         m.bt_lines(coef, r, "x", x=r)
     with pytest.raises(ValueError):
         m.bt_lines(coef[:, :3], r, "x")
-    with pytest.raises(KeyError):
+    with pytest.raises(ValueError, match="axis"):
         m.bt_lines(coef, r, "w")
 
 
