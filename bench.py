@@ -37,6 +37,8 @@ Also reported on the same line:
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 2]
     python bench.py --roofline-only      (kernel loops only, for profiling)
+    python bench.py --oracle-times       (the CPU oracle on one unit of
+                                          every workload; no GPU)
     python bench.py --workloads-only [--workloads ssor,var7,...]
                                          (those workloads only)
 """
@@ -100,6 +102,9 @@ def parse():
                     default="ssor,var7,jacobi,penta,bt,ilu,xline,probe512",
                     help="which of them: ssor, var7, jacobi, penta, bt, ilu, "
                          "xline, probe512 (comma-separated)")
+    ap.add_argument("--oracle-times", action="store_true",
+                    help="time the single-threaded CPU oracle on one unit of "
+                         "every workload (no GPU) and exit")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the kernel loops and a copy calibration")
     return ap.parse_args()
@@ -392,6 +397,82 @@ def var7_workload(torch, m, inputs, dev, reps):
     return out
 
 
+def oracle_times():
+    """The CPU oracle (one thread) on one unit of every workload, beside
+    which the GPU figures are read: seconds per unit and what the unit is."""
+    import numpy as np
+
+    import oracle
+    from paper_2204_13304_amd import inputs
+
+    def timed(fn):
+        t = time.perf_counter()
+        fn()
+        return time.perf_counter() - t
+
+    out = {}
+
+    def rec(key, unit, sec):
+        out[key] = {"seconds": sec, "unit": unit}
+        log(f"oracle {key}: {sec:.3f} s ({unit})")
+
+    b16 = oracle.spmv27(np.ones((16,) * 3))
+    rec("c1_symgs_pcg_16", "50 SymGS-PCG iterations at 16^3",
+        timed(lambda: oracle.pcg(b16, precond="symgs", max_iter=50)))
+    b104 = oracle.spmv27(np.ones((104,) * 3)) + inputs.rhs_perturbation(
+        2, (104,) * 3)
+    rec("c2_mg_pcg_104", "50 MG-PCG iterations at 104^3, 4 levels",
+        timed(lambda: oracle.pcg(b104, precond="mg", levels=4, max_iter=50)))
+    b256 = oracle.spmv27(np.ones((256,) * 3)) + inputs.rhs_perturbation(
+        3, (256,) * 3)
+    t1 = timed(lambda: oracle.pcg(b256, precond="mg", levels=4, max_iter=1))
+    t2 = timed(lambda: oracle.pcg(b256, precond="mg", levels=4, max_iter=2))
+    rec("c3_mg_pcg_256", "one MG-PCG iteration at 256^3, 4 levels "
+        "(2-iteration minus 1-iteration run)", t2 - t1)
+    rr = inputs.standard_normal(10, (256,) * 3)
+    xx = inputs.standard_normal(11, (256,) * 3)
+    rec("c3_symgs_256", "one SymGS (forward + backward) at 256^3",
+        timed(lambda: oracle.symgs27(rr, xx, "sym")))
+    del b256, rr, xx
+    blk = inputs.block7_blocks(4)
+    b7 = oracle.spmv_block7(np.ones((162, 162, 162, 5)), blk)
+    rec("c4_ssor_162", "one block SSOR iteration (forward + backward) at "
+        "162^3 x 5", timed(lambda: oracle.ssor_block7(
+            b7, np.zeros_like(b7), blk, 1.2, "sym")))
+    del b7
+    pr = inputs.var7_problem(5, (128,) * 3)
+    fc = (pr["kx"], pr["ky"], pr["kz"])
+    t1 = timed(lambda: oracle.pcg(pr["f"], kind="var7", faces=fc,
+                                  precond="mg", levels=4, max_iter=1))
+    t2 = timed(lambda: oracle.pcg(pr["f"], kind="var7", faces=fc,
+                                  precond="mg", levels=4, max_iter=2))
+    rec("c5_var7_mg_pcg_128", "one VAR7 MG-PCG iteration at 128^3, 4 "
+        "levels (2-iteration minus 1-iteration run)", t2 - t1)
+    del pr
+    bj = inputs.standard_normal(33, (4096, 4096))
+    rec("jacobi9_4096", "8 Jacobi iterations at 4096^2",
+        timed(lambda: oracle.jacobi9(bj, np.zeros_like(bj), 8)))
+    del bj
+    cp = inputs.uniform(42, (5,) + (162,) * 3)
+    cp[2] += 6.0
+    rp = inputs.standard_normal(43, (162,) * 3)
+    rec("penta_162_x", "pentadiagonal lines along x at 162^3",
+        timed(lambda: oracle.penta_lines(cp, rp, "x")))
+    del cp, rp
+    cb, rb = inputs.bt_problem(70, (162,) * 3)
+    rec("bt_162_x", "5x5 block-tridiagonal lines along x at 162^3",
+        timed(lambda: oracle.bt_lines(cb, rb, "x")))
+    del cb, rb
+    ri = inputs.standard_normal(52, (256,) * 3)
+
+    def ilu():
+        d = oracle.ilu27_factor((256,) * 3)
+        oracle.ilu27_solve(d, ri)
+    rec("ilu27_256", "ILU factor and one application at 256^3", timed(ilu))
+    return {"oracle_times": out, "threads": 1,
+            "host": f"{cpu_model()}, {os.cpu_count()} CPUs"}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -495,6 +576,9 @@ def main():
                           "1 (sharding the sweeps over several GPUs, as "
                           "z-slab pipelines, is not built)"}))
         return 2
+    if args.oracle_times:
+        print(json.dumps(oracle_times()))
+        return 0
     import numpy as np
     import torch
 
