@@ -118,3 +118,34 @@ def test_line_solves_reject_a_bad_axis():
     with pytest.raises(ValueError, match="axis"):
         m.penta_lines(torch.zeros((5, 2, 2, 2), dtype=torch.float64),
                       r[..., 0], 3)
+
+
+@pytest.mark.parametrize("fn,nc,nw", [("m2s_penta_lines", 5, 2),
+                                      ("m2s_bt_lines", 75, 25)])
+def test_line_solve_argument_errors(fn, nc, nw):
+    """Validation happens on the host before anything is launched, so the
+    error paths run without a GPU; overlap checks are pointer arithmetic
+    (the addresses below are never dereferenced).  Every call here must
+    fail validation: one that passed would launch on these fake addresses."""
+    lib = L.load()
+    f = getattr(lib, fn)
+    nx, ny, nz = 4, 5, 6
+    nb = 8 * nx * ny * nz * (5 if fn == "m2s_bt_lines" else 1)  # r, x
+    cb = 8 * nx * ny * nz * nc
+    wb = 8 * nx * ny * nz * nw
+    base = 1 << 40
+    coef, r = base, base + cb
+    x, work = r + nb, r + 2 * nb
+    P = C.c_void_p
+
+    def call(nx_, ny_, nz_, axis, c, rr, xx, w):
+        return f(nx_, ny_, nz_, axis, P(c), P(rr), P(xx), P(w), None)
+    assert call(nx, ny, nz, 0, None, r, x, work) == 1   # ARG: null
+    assert call(nx, ny, nz, 3, coef, r, x, work) == 1   # ARG: axis
+    assert call(nx, ny, nz, -1, coef, r, x, work) == 1
+    assert call(0, ny, nz, 0, coef, r, x, work) == 2    # SHAPE
+    assert call(1 << 16, 1 << 15, 1, 0, coef, r, x, work) == 2  # n >= 2^31
+    assert call(nx, ny, nz, 1, coef, r, r, work) == 4   # ALIAS: x = r
+    assert call(nx, ny, nz, 1, coef, r, x, x + 8) == 4  # work overlaps x
+    assert call(nx, ny, nz, 2, coef, coef + cb - 8, x, work) == 4  # r in coef
+    assert call(nx, ny, nz, 2, coef, r, x, coef + cb - wb // 2) == 4
