@@ -297,7 +297,10 @@ m2s_status m2s_face_grad(const m2s_stencil *A, const double *u,
 
 /* ---------------------------------------------------------------------
  * Small vector kernels used around the solvers (double, device):
- * m2s_dot writes x.y (fixed-order two-stage reduction) to *out (device).
+ * m2s_dot writes x.y (fixed-order two-stage reduction) to *out (device);
+ *   each call takes its own partials buffer from the stream-ordered
+ *   allocator (hipMallocAsync / hipFreeAsync on `stream`), so concurrent
+ *   calls do not share scratch.  n >= 0; M2S_ERR_HIP if that fails.
  * m2s_convert copies n elements between F64 and F32 (round to nearest).
  * --------------------------------------------------------------------- */
 m2s_status m2s_dot(const double *x, const double *y, int64_t n, double *out,
