@@ -366,7 +366,7 @@ const char *m2s_status_string(m2s_status s)
     return "unknown status";
 }
 
-int m2s_version(void) { return 10000; }
+int m2s_version(void) { return 10100; }  // 1.1.0: m2s_bt_lines added
 
 m2s_status m2s_plan_sweep(const m2s_stencil *A, m2s_sweep_plan *plan)
 {
