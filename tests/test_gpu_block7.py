@@ -115,3 +115,24 @@ def test_ssor_rejects_bad_omega(m):
     x = torch.zeros((4, 4, 4, 5), dtype=torch.float64, device="cuda")
     with pytest.raises(RuntimeError):
         m.ssor_sweep(A, x.clone(), x, 2.5, "sym")
+
+
+def test_tile_wait_timeout_is_reported_and_recovered(m, monkeypatch):
+    # as for the 27-point tiles: a forced time-out is latched and reported,
+    # and the workspace is usable afterwards
+    shape = (12, 40, 8)
+    banner("ssor forced tile wait time-out")
+    B = inputs.block7_blocks(4)
+    A = m.block7(shape, B)
+    ws = m.Workspace(A)
+    b = inputs.standard_normal(71, shape + (5,))
+    x0 = inputs.standard_normal(72, shape + (5,))
+    monkeypatch.setenv("M2S_SPIN_LIMIT", "1")
+    m.ssor_sweep(A, dev(b), dev(x0), 1.2, "fwd", ws)
+    with pytest.raises(RuntimeError, match="M2S_ERR_TIMEOUT"):
+        ws.check()
+    monkeypatch.delenv("M2S_SPIN_LIMIT")
+    xg = dev(x0)
+    m.ssor_sweep(A, dev(b), xg, 1.2, "sym", ws)
+    ws.check()
+    assert rel_inf(host(xg), oracle.ssor_block7(b, x0, B, 1.2, "sym")) <= 1e-13

@@ -164,3 +164,25 @@ def test_full_size_symgs_512_forward(m):
     got = host(out)
     del out
     assert rel_inf(got, oracle.symgs27(r, x0, "fwd")) <= 1e-13
+
+
+def test_tile_wait_timeout_is_reported_and_recovered(m, monkeypatch):
+    # a spin limit of one poll makes a tile give up waiting for a producer
+    # tile's boundary records: every role of every workgroup leaves its step
+    # loop together, the latch reports the time-out, and the workspace works
+    # afterwards
+    shape = (24, 40, 12)
+    banner("symgs27 forced tile wait time-out")
+    A = m.const27(shape)
+    ws = m.Workspace(A)
+    r = inputs.standard_normal(66, shape)
+    x0 = inputs.standard_normal(67, shape)
+    monkeypatch.setenv("M2S_SPIN_LIMIT", "1")
+    m.symgs(A, dev(r), dev(x0), "fwd", ws)
+    with pytest.raises(RuntimeError, match="M2S_ERR_TIMEOUT"):
+        ws.check()
+    monkeypatch.delenv("M2S_SPIN_LIMIT")
+    xg = dev(x0)
+    m.symgs(A, dev(r), xg, "sym", ws)
+    ws.check()
+    assert rel_inf(host(xg), oracle.symgs27(r, x0, "sym")) <= 1e-13

@@ -278,3 +278,25 @@ def test_solve_gradient_full_size_128(m):
     kg = sum(float(np.sum(kk * gg)) for kk, gg in zip(k, g))
     scale = sum(float(np.sum(np.abs(kk * gg))) for kk, gg in zip(k, g))
     assert abs(kg + float(np.dot(lam.ravel(), Au.ravel()))) <= 1e-11 * scale
+
+
+def test_tile_wait_timeout_is_reported_and_recovered(m, monkeypatch):
+    # as for the 27-point tiles: a forced time-out is latched and reported,
+    # and the workspace is usable afterwards
+    shape = (16, 40, 10)
+    banner("var7 forced tile wait time-out")
+    pr = inputs.var7_problem(68, shape)
+    A = _A(m, pr)
+    ws = m.Workspace(A)
+    r = inputs.standard_normal(69, shape)
+    x0 = inputs.standard_normal(70, shape)
+    monkeypatch.setenv("M2S_SPIN_LIMIT", "1")
+    m.symgs(A, dev(r), dev(x0), "fwd", ws)
+    with pytest.raises(RuntimeError, match="M2S_ERR_TIMEOUT"):
+        ws.check()
+    monkeypatch.delenv("M2S_SPIN_LIMIT")
+    xg = dev(x0)
+    m.symgs(A, dev(r), xg, "sym", ws)
+    ws.check()
+    ref = oracle.symgs_var7(r, x0, pr["kx"], pr["ky"], pr["kz"], "sym")
+    assert rel_inf(host(xg), ref) <= 1e-13
