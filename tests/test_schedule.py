@@ -4,7 +4,9 @@ the three tiled sweep kernels (27-point, VAR7, block SSOR) that replay each
 kernel's index arithmetic step by step on symbolic values, checking that
 every read of the lexicographic sweep sees the right value, that no two
 wavefronts race on a slot, and that the tilings match what libm2s.so plans
-(m2s_plan_sweep)."""
+(m2s_plan_sweep); and a model of the tiles' hand-off protocol (tickets in
+dependency order, epoch-tagged records, bounded waits) with fault
+injection: a withheld record must end in a latched time-out, not a hang."""
 import itertools
 import json
 import os
@@ -670,3 +672,104 @@ def test_v7_plan_matches_tile_model(shape, monkeypatch):
         # nw compute + nw memory wavefronts + 1 poll wavefront
         assert p["threads"] == 64 * (2 * nw + 1)
         assert p["nslabs"] == -(-ny // V7_TJ) * -(-nz // (4 * nw))
+
+
+# ------------------------------------------------------------------------
+# The hand-off protocol of the tiled sweeps, as a CPU model: workgroups take
+# tickets in the tile list's (dependency) order; a tile waits, with a
+# bounded number of polls that also watch the error word, for the records
+# of the tiles its lower neighbours lie in, each record carrying the epoch
+# of the launch that wrote it; records are never reset between launches.
+def _simulate_launch(tiles, deps, records, epoch, n_groups, spin_limit,
+                     withhold=None, max_rounds=100000):
+    """Round-robin over n_groups workgroups (a generator each, one action
+    per turn).  Returns (tiles completed, error latched, rounds taken)."""
+    state = {"ticket": 0, "err": False}
+    done = set()
+
+    def group():
+        while True:
+            tk = state["ticket"]
+            state["ticket"] += 1
+            if tk >= len(tiles) or state["err"]:
+                return
+            tile = tiles[tk]
+            for prod in deps[tile]:
+                budget = spin_limit
+                while records.get(prod) != epoch:
+                    budget -= 1
+                    if budget < 0 or state["err"]:
+                        state["err"] = True
+                        break
+                    yield  # sleep, then poll again
+                if state["err"]:
+                    break
+                yield
+            if state["err"]:
+                continue  # back to the ticket loop, which returns
+            if tile != withhold:
+                records[tile] = epoch  # publish once per launch
+            done.add(tile)
+            yield
+
+    gens = [group() for _ in range(n_groups)]
+    rounds = 0
+    while gens:
+        rounds += 1
+        assert rounds < max_rounds, "the launch did not drain"
+        for g in list(gens):
+            try:
+                next(g)
+            except StopIteration:
+                gens.remove(g)
+    return done, state["err"], rounds
+
+
+def _c27_tile_graph(shape, kt):
+    tiles = c27_tile_list(shape, kt)
+    have = set(tiles)
+    deps = {t: [p for p in ((t[0] - 1, t[1]), (t[0], t[1] - 1),
+                            (t[0] - 1, t[1] - 1)) if p in have]
+            for t in tiles}
+    return tiles, deps
+
+
+@pytest.mark.parametrize("n_groups", [1, 3, 64])
+def test_protocol_completes_without_co_residency(n_groups):
+    # every producer holds an earlier ticket, so the chain of waits ends at
+    # a running workgroup: any number of workgroups (even one) finishes
+    tiles, deps = _c27_tile_graph((23, 40, 5), 8)
+    records = {}
+    done, err, _ = _simulate_launch(tiles, deps, records, 1, n_groups,
+                                    spin_limit=10 ** 6)
+    assert not err and done == set(tiles)
+
+
+@pytest.mark.parametrize("n_groups", [1, 5, 64])
+def test_protocol_withheld_record_times_out_and_drains(n_groups):
+    # a record that is never published (fault injection) ends every
+    # workgroup with the error latched; no tile that depends on it, directly
+    # or through others, completes
+    tiles, deps = _c27_tile_graph((23, 40, 5), 8)
+    bad = tiles[len(tiles) // 3]
+    records = {}
+    done, err, _ = _simulate_launch(tiles, deps, records, 1, n_groups,
+                                    spin_limit=50, withhold=bad)
+    assert err
+    later = {t for t in tiles if t[0] >= bad[0] and t[1] >= bad[1]}
+    assert not (done & (later - {bad}))
+
+
+def test_protocol_records_of_an_earlier_launch_are_not_taken():
+    # records are never reset: a second launch must not accept the first
+    # launch's records, which carry the old epoch
+    tiles, deps = _c27_tile_graph((16, 16, 16), 4)
+    records = {}
+    done, err, _ = _simulate_launch(tiles, deps, records, 1, 8, 10 ** 6)
+    assert not err and done == set(tiles)
+    bad = tiles[len(tiles) // 2]
+    done, err, _ = _simulate_launch(tiles, deps, records, 2, 8, 50,
+                                    withhold=bad)
+    assert err and records[bad] == 1
+    later = {t for t in tiles if t[0] >= bad[0] and t[1] >= bad[1]}
+    assert not (done & (later - {bad}))
