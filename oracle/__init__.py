@@ -26,7 +26,10 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIBPATH = os.path.join(_HERE, "libm2s_oracle.so")
+# M2S_ORACLE_LIB selects another build of the same source (e.g. one made
+# with -fsanitize=address,undefined to check the oracle itself)
+_LIBPATH = os.environ.get("M2S_ORACLE_LIB") or os.path.join(
+    _HERE, "libm2s_oracle.so")
 _lib = None
 
 PC_NONE, PC_SYMGS, PC_MG, PC_MG_F32 = 0, 1, 2, 3

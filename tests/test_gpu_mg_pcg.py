@@ -172,6 +172,31 @@ def test_pcg_var7(m):
     assert rel_inf(host(u), ref["x"]) <= 1e-8
 
 
+def test_pcg_non_finite_rhs_reported(m):
+    # a NaN in b makes the initial residual non-finite: reported as a
+    # breakdown before any iteration, not iterated on
+    shape = (8, 8, 8)
+    A = m.const27(shape)
+    b = np.ones(shape)
+    b[3, 4, 5] = np.nan
+    _, info = m.pcg_solve(A, dev(b), None, "none", max_iter=10, rtol=1e-9,
+                          raise_on_error=False)
+    assert info["status"] == "M2S_ERR_BREAKDOWN" and info["iters"] == 0
+
+
+def test_pcg_warm_start_resumes(m):
+    # resume = call again with the last x as x0: 10 + 10 iterations reach
+    # the residual of 20 from zero to rounding (CG restarts, so compare
+    # convergence, not bits)
+    shape = (16, 16, 16)
+    A = m.const27(shape)
+    b = dev(oracle.spmv27(np.ones(shape)))
+    x, i1 = m.pcg_solve(A, b, None, "symgs", max_iter=10, rtol=0.0)
+    x, i2 = m.pcg_solve(A, b, x, "symgs", max_iter=10, rtol=0.0)
+    assert i2["true_rel_res"] < i1["true_rel_res"] * 1e-3
+    assert np.max(np.abs(host(x) - 1.0)) <= 1e-6
+
+
 def test_pcg_breakdown_reported(m):
     shape = (8, 8, 8)
     A = m.const27(shape, diag=-26.0)
