@@ -149,3 +149,17 @@ def test_line_solve_argument_errors(fn, nc, nw):
     assert call(nx, ny, nz, 1, coef, r, x, x + 8) == 4  # work overlaps x
     assert call(nx, ny, nz, 2, coef, coef + cb - 8, x, work) == 4  # r in coef
     assert call(nx, ny, nz, 2, coef, r, x, coef + cb - wb // 2) == 4
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU only: --gpus N > 1 exits with a message instead of a number
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "bench.py", "--gpus", "2"],
+                         cwd=root, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 2
+    msg = json.loads(out.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
