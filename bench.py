@@ -35,7 +35,7 @@ Also reported on the same line:
                     the x-line scan variant of the 27-point sweep (256^3);
                     the 27-point sweep and SpMV at 512^3 (beyond the MALL).
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 2]
+    python bench.py [--gpus 1] [--steps 50] [--warmup 3]
     python bench.py --roofline-only      (kernel loops only, for profiling)
     python bench.py --oracle-times       (the CPU oracle on one unit of
                                           every workload; no GPU)
@@ -84,8 +84,8 @@ def measured_traffic(profile=SWEEP_PROFILE):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--reps", type=int, default=20,

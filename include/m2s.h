@@ -256,7 +256,12 @@ void m2s_mg_destroy(m2s_mg *mg);
  * MG (needs `mg` built on the same operator).  x holds x0 on entry and the
  * solution on return.  Synchronises `stream`.  Returns M2S_OK on
  * convergence (or after max_iter with rtol <= 0), M2S_ERR_NOT_CONVERGED,
- * M2S_ERR_BREAKDOWN, M2S_ERR_TIMEOUT.
+ * M2S_ERR_BREAKDOWN, M2S_ERR_TIMEOUT.  Each iteration's scalars are read
+ * back for the convergence and breakdown tests, except in a fixed-iteration
+ * run (rtol <= 0) without history or residual replacement: there the host
+ * does not wait per iteration, a breakdown (p.Ap <= 0 or a non-finite
+ * scalar) is latched on the device and reported after the last iteration,
+ * and iters is then max_iter.
  * --------------------------------------------------------------------- */
 typedef enum {
     M2S_PC_NONE = 0,

@@ -1088,6 +1088,7 @@ extern "C" m2s_status m2s_pcg_solve(const m2s_stencil *A,
     const double normr0 = std::sqrt(hsc[SC_RR]);
     double normr = normr0;
     m2s_status result = M2S_ERR_NOT_CONVERGED;
+    const bool lazy = opts->rtol <= 0 && opts->replace_every <= 0 && !hist;
     int it = 0;
     if (hist) hist[0] = 1.0;
     if (!std::isfinite(normr0)) result = M2S_ERR_BREAKDOWN;
@@ -1119,11 +1120,16 @@ extern "C" m2s_status m2s_pcg_solve(const m2s_stencil *A,
                                     stream));
             M2S_TRY(launch_update_xr(x, B.r, B.p, B.ap, n, B.sc, B.partials,
                                      stream));
+            // a fixed-iteration run without history or replacement has no
+            // test to make before its last iteration: the scalars stay on
+            // the device (a breakdown is latched there) and the host does
+            // not wait for each iteration
+            if (lazy && it < opts->max_iter) continue;
             if ((st = fetch()) != M2S_OK) return st;
             const double pap = hsc[SC_PAP];
             normr = std::sqrt(hsc[SC_RR]);
-            if (!(pap > 0.0) || !std::isfinite(pap) || !std::isfinite(normr) ||
-                !std::isfinite(hsc[SC_RZ])) {
+            if (hsc[SC_BD] != 0.0 || !(pap > 0.0) || !std::isfinite(pap) ||
+                !std::isfinite(normr) || !std::isfinite(hsc[SC_RZ])) {
                 result = M2S_ERR_BREAKDOWN;
                 break;
             }

@@ -536,7 +536,11 @@ __global__ void __launch_bounds__(256)
                      const double *__restrict__ ap, int64_t n, double *sc,
                      double *partials, unsigned *counter)
 {
-    const double alpha = sc[SC_RZ] / sc[SC_PAP];
+    const double rz = sc[SC_RZ], pap = sc[SC_PAP];
+    const double alpha = rz / pap;
+    if (blockIdx.x == 0 && threadIdx.x == 0 &&
+        (!(pap > 0.0) || !isfinite(pap) || !isfinite(rz)))
+        sc[SC_BD] = 1.0;
     double acc = 0.0;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x) {

@@ -330,8 +330,10 @@ hipError_t launch_bt_lines(int nx, int ny, int nz, int axis,
 inline size_t c27_record_bytes(m2s_dtype t) { return t == M2S_F64 ? 16 : 8; }
 
 // CG vector kernels (double).  Scalars live in a small device array `sc`.
+// SC_BD latches a breakdown (p.Ap <= 0 or a non-finite r.z, p.Ap) on the
+// device, so that a solve need not read the scalars back every iteration.
 enum CgScalar {
-    SC_RZ = 0, SC_RZ_OLD, SC_PAP, SC_RR, SC_ALPHA, SC_BETA, SC_TMP, SC_N
+    SC_RZ = 0, SC_RZ_OLD, SC_PAP, SC_RR, SC_BD, SC_N
 };
 int dot_partials_capacity();
 hipError_t launch_dot(const double *x, const double *y, int64_t n,

@@ -201,6 +201,18 @@ def test_pcg_warm_start_resumes(m):
     assert np.max(np.abs(host(x) - 1.0)) <= 1e-6
 
 
+def test_pcg_breakdown_latched_in_fixed_iteration_run(m):
+    # rtol <= 0 without history: the scalars are read back only after the
+    # last iteration, so the breakdown is latched on the device and
+    # reported then
+    shape = (8, 8, 8)
+    A = m.const27(shape, diag=-26.0)
+    b = dev(np.ones(shape))
+    _, info = m.pcg_solve(A, b, None, "none", max_iter=10, rtol=0.0,
+                          raise_on_error=False)
+    assert info["status"] == "M2S_ERR_BREAKDOWN" and info["iters"] == 10
+
+
 def test_pcg_breakdown_reported(m):
     shape = (8, 8, 8)
     A = m.const27(shape, diag=-26.0)
