@@ -228,8 +228,10 @@ m2s_status m2s_ssor_sweep_sequential(const m2s_stencil *A, const void *b,
  * "HPCG Prolong" matrix of Table 1); per level z = 0, one SymGS, fused
  * residual + restriction, recurse, prolongation, one SymGS; the coarsest
  * level runs one SymGS from zero.  CONST27 keeps the same stencil on every
- * level; VAR7 coarse faces are the series combination of the two fine faces
- * they span, scaled by 1/4 for the doubled spacing.
+ * level; a VAR7 coarse face gets half the conductance that exact
+ * elimination of the fine points it spans gives on a 1-D line: ab/(2(a+b))
+ * for two fine faces a, b in series (interior and last faces), k0/2 for the
+ * first face, which spans fine face 0 alone.
  * prec = M2S_F32 runs the whole V-cycle in float (stored and computed):
  * m2s_mg_vcycle then takes r and returns z in DOUBLE and converts at the
  * boundary.  With prec = M2S_F64 r and z are double.

@@ -13,10 +13,9 @@ modify their inputs; "in-place" sweeps work on a copy that is returned.
 
 Each wrapped routine cites the part of the paper it follows in the C source.
 
-Parity unpinned: var7_coarsen, the VAR7 coarse-face rule (the paper gives no
-coarse operator for variable coefficients; the rule is a reading, pinned
-only by its constant-coefficient case, the symmetry of the coarse operator
-and the convergence of the multigrid built on it).
+Every routine is pinned by a CPU test against something other than itself
+(assembled sparse matrices, dense triangular solves, closed forms, exact
+1-D elimination, finite differences); see the tests named test_oracle_*.
 """
 from __future__ import annotations
 
@@ -197,6 +196,43 @@ def var7_face_grad(u, lam, dtype=np.float64):
     gz = np.empty((nz + 1, ny, nx), dtype)
     _fn("var7_face_grad", dtype)(nx, ny, nz, u, lam, gx, gy, gz)
     return gx, gy, gz
+
+
+# ------------------------------------------------------- sweep adjoints
+def symgs_adjoint(g, direction="fwd", kind="const27", faces=None, diag=26.0,
+                  off=-1.0):
+    """Gradients (gr, gx) of <g, S(r, x)> for the lexicographic sweep S of a
+    symmetric operator A = D + L + U (the transposed sweeps in reverse
+    order).  A forward sweep is x' = (D+L)^{-1} (r - U x), so
+        gr = (D+L)^{-T} g,   gx = -U^T gr;
+    with A symmetric (D+L)^T = D+U and U^T = L: gr is a backward sweep of g
+    from zero and gx = -L gr.  A backward sweep x' = (D+U)^{-1} (r - L x)
+    likewise gives gr = forward sweep of g from zero, gx = -U gr.  The
+    symmetric sweep (forward, then backward) chains the two in reverse:
+    the backward sweep's gradients first, its gx fed to the forward one;
+    gr is the sum of both gr's."""
+    g = _c(g, np.float64)
+    zero = np.zeros_like(g)
+    if kind == "const27":
+        sweep = lambda rhs, d: symgs27(rhs, zero, d, diag, off)  # noqa: E731
+        part = lambda v, s: spmv27_part(v, s, off)  # noqa: E731
+    elif kind == "var7":
+        kx, ky, kz = faces
+        sweep = lambda rhs, d: symgs_var7(rhs, zero, kx, ky, kz, d)  # noqa
+        part = lambda v, s: spmv_var7_part(v, kx, ky, kz, s)  # noqa: E731
+    else:
+        raise ValueError(kind)
+    if direction == "fwd":
+        gr = sweep(g, "bwd")
+        return gr, -part(gr, -1)
+    if direction == "bwd":
+        gr = sweep(g, "fwd")
+        return gr, -part(gr, +1)
+    if direction == "sym":
+        grb, gmid = symgs_adjoint(g, "bwd", kind, faces, diag, off)
+        grf, gx = symgs_adjoint(gmid, "fwd", kind, faces, diag, off)
+        return grb + grf, gx
+    raise ValueError(direction)
 
 
 # ---------------------------------------------------------------- BLOCK7

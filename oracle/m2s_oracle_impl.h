@@ -242,13 +242,20 @@ void FN(symgs_var7_bwd)(int nx, int ny, int nz, const REAL *kx,
 
 /* Coarse VAR7 coefficients for a grid coarsened by 2 per axis with
  * injection (coarse point I sits on fine point 2I).  The paper fixes no rule
- * for this; the reading used here: a coarse face joining coarse points I-1
- * and I spans the two fine faces 2I-1 and 2I; their series combination
- * (harmonic mean) is rescaled by 1/4 for the doubled spacing.  The first
- * coarse face on an axis only covers fine face 0; the last one covers fine
- * faces nf-1 and nf.  Transverse position: the fine face row through the
- * coincident fine points (2J, 2K). */
-static inline REAL CAT(hm4_, SFX)(REAL a, REAL b)
+ * for this; the reading used here: each coarse face gets 1/2 of the
+ * conductance that exact elimination of the fine points between the two
+ * coarse points (or between the coarse point and the Dirichlet ghost) gives
+ * on a 1-D line, i.e. of the Schur complement of D^T K D (Sec. 4.1) onto the
+ * even points.  Two fine faces a, b in series give ab/(a+b), so an interior
+ * coarse face I (fine faces 2I-1 and 2I) and the last one (fine faces nf-1
+ * and nf) get ab/(2(a+b)), a quarter of their harmonic mean.  The first
+ * coarse face has no fine point to eliminate: fine point 0 is coarse point
+ * 0 and touches the ghost through fine face 0 alone, so it gets k0/2.  The
+ * factor 1/2 is one constant on every face: it is 1/4 for the injected
+ * residual (the operator carries no 1/h^2) times 2 for the coarse face being
+ * twice the fine face in area per unit length.  Transverse position: the
+ * fine face row through the coincident fine points (2J, 2K). */
+static inline REAL CAT(half_series_, SFX)(REAL a, REAL b)
 {
     return (a * b) / ((REAL)2 * (a + b));
 }
@@ -261,27 +268,27 @@ void FN(var7_coarsen)(int nx, int ny, int nz, const REAL *kx, const REAL *ky,
         for (int J = 0; J < cy; ++J)
             for (int I = 0; I <= cx; ++I) {
                 REAL v;
-                if (I == 0) v = KX(0, 2 * J, 2 * K) / (REAL)4;
-                else v = CAT(hm4_, SFX)(KX(2 * I - 1, 2 * J, 2 * K),
-                                        KX(2 * I, 2 * J, 2 * K));
+                if (I == 0) v = KX(0, 2 * J, 2 * K) / (REAL)2;
+                else v = CAT(half_series_, SFX)(KX(2 * I - 1, 2 * J, 2 * K),
+                                                KX(2 * I, 2 * J, 2 * K));
                 kxc[((long)K * cy + J) * (cx + 1) + I] = v;
             }
     for (int K = 0; K < cz; ++K)
         for (int J = 0; J <= cy; ++J)
             for (int I = 0; I < cx; ++I) {
                 REAL v;
-                if (J == 0) v = KY(2 * I, 0, 2 * K) / (REAL)4;
-                else v = CAT(hm4_, SFX)(KY(2 * I, 2 * J - 1, 2 * K),
-                                        KY(2 * I, 2 * J, 2 * K));
+                if (J == 0) v = KY(2 * I, 0, 2 * K) / (REAL)2;
+                else v = CAT(half_series_, SFX)(KY(2 * I, 2 * J - 1, 2 * K),
+                                                KY(2 * I, 2 * J, 2 * K));
                 kyc[((long)K * (cy + 1) + J) * cx + I] = v;
             }
     for (int K = 0; K <= cz; ++K)
         for (int J = 0; J < cy; ++J)
             for (int I = 0; I < cx; ++I) {
                 REAL v;
-                if (K == 0) v = KZ(2 * I, 2 * J, 0) / (REAL)4;
-                else v = CAT(hm4_, SFX)(KZ(2 * I, 2 * J, 2 * K - 1),
-                                        KZ(2 * I, 2 * J, 2 * K));
+                if (K == 0) v = KZ(2 * I, 2 * J, 0) / (REAL)2;
+                else v = CAT(half_series_, SFX)(KZ(2 * I, 2 * J, 2 * K - 1),
+                                                KZ(2 * I, 2 * J, 2 * K));
                 kzc[((long)K * cy + J) * cx + I] = v;
             }
 }

@@ -340,12 +340,13 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-// Coarse VAR7 faces: interior coarse face I spans fine faces 2I-1 and 2I,
-// combined in series, over doubled spacing: ab / (2 (a + b)); the first
-// face on an axis covers fine face 0 only (value / 4); transverse position
-// on the coincident fine row.
+// Coarse VAR7 faces: half the conductance of the fine segment a coarse face
+// spans, eliminated exactly on a 1-D line.  Interior and last faces span two
+// fine faces in series: ab / (2 (a + b)); the first face on an axis spans
+// fine face 0 only (coarse point 0 is fine point 0): k0 / 2.  Transverse
+// position on the coincident fine row.
 template <typename T>
-__device__ __forceinline__ T hm4(T a, T b)
+__device__ __forceinline__ T half_series(T a, T b)
 {
     return (a * b) / (T(2) * (a + b));
 }
@@ -364,25 +365,25 @@ __global__ void __launch_bounds__(256)
             const int I = (int)(e % (gc.nx + 1));
             const int64_t t = e / (gc.nx + 1);
             const int J = (int)(t % gc.ny), K = (int)(t / gc.ny);
-            kxc[e] = I == 0 ? kx[Ff.ix(0, 2 * J, 2 * K)] / T(4)
-                            : hm4(kx[Ff.ix(2 * I - 1, 2 * J, 2 * K)],
-                                  kx[Ff.ix(2 * I, 2 * J, 2 * K)]);
+            kxc[e] = I == 0 ? kx[Ff.ix(0, 2 * J, 2 * K)] / T(2)
+                            : half_series(kx[Ff.ix(2 * I - 1, 2 * J, 2 * K)],
+                                          kx[Ff.ix(2 * I, 2 * J, 2 * K)]);
         } else if (e < nx + ny) {
             const int64_t f = e - nx;
             const int I = (int)(f % gc.nx);
             const int64_t t = f / gc.nx;
             const int J = (int)(t % (gc.ny + 1)), K = (int)(t / (gc.ny + 1));
-            kyc[f] = J == 0 ? ky[Ff.iy(2 * I, 0, 2 * K)] / T(4)
-                            : hm4(ky[Ff.iy(2 * I, 2 * J - 1, 2 * K)],
-                                  ky[Ff.iy(2 * I, 2 * J, 2 * K)]);
+            kyc[f] = J == 0 ? ky[Ff.iy(2 * I, 0, 2 * K)] / T(2)
+                            : half_series(ky[Ff.iy(2 * I, 2 * J - 1, 2 * K)],
+                                          ky[Ff.iy(2 * I, 2 * J, 2 * K)]);
         } else {
             const int64_t f = e - nx - ny;
             const int I = (int)(f % gc.nx);
             const int64_t t = f / gc.nx;
             const int J = (int)(t % gc.ny), K = (int)(t / gc.ny);
-            kzc[f] = K == 0 ? kz[Ff.iz(2 * I, 2 * J, 0)] / T(4)
-                            : hm4(kz[Ff.iz(2 * I, 2 * J, 2 * K - 1)],
-                                  kz[Ff.iz(2 * I, 2 * J, 2 * K)]);
+            kzc[f] = K == 0 ? kz[Ff.iz(2 * I, 2 * J, 0)] / T(2)
+                            : half_series(kz[Ff.iz(2 * I, 2 * J, 2 * K - 1)],
+                                          kz[Ff.iz(2 * I, 2 * J, 2 * K)]);
         }
     }
 }

@@ -1,5 +1,6 @@
 """GPU parity of the VAR7 operator (SpMV, sweeps, strict parts), the sweep
-adjoints (dot-product identity against the forward sweep), the face-
+adjoints (element by element against the oracle's transposed sweeps, and
+the dot-product identity against the forward sweep), the face-
 coefficient gradient kernel, and the autograd solve (adjoint MG-PCG +
 face gradient) against finite differences and the oracle gradient, and at
 the benchmark's 128^3 size by its residuals and the face-gradient identity."""
@@ -140,6 +141,30 @@ def test_var7_float32(m):
     ref = oracle.symgs_var7(r, np.zeros(shape), pr["kx"], pr["ky"],
                             pr["kz"], "sym")
     assert rel_inf(host(xg), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("kind", ["const27", "var7"])
+@pytest.mark.parametrize("direction", ["fwd", "bwd", "sym"])
+@pytest.mark.parametrize("shape", [(9, 10, 11), (6, 40, 37), (20, 33, 5)])
+def test_sweep_adjoint_parity(m, kind, direction, shape):
+    # gr and gx element by element against the oracle's transposed sweeps
+    # run in reverse order, on shapes spanning several tiles with ragged
+    # tails (tiles of 16 rows by 4-8 planes)
+    banner(f"sweep adjoint {kind} {direction} {shape}")
+    if kind == "const27":
+        A = m.const27(shape)
+        ref = oracle.symgs_adjoint(inputs.standard_normal(17, shape),
+                                   direction)
+    else:
+        pr = inputs.var7_problem(26, shape)
+        A = _A(m, pr)
+        ref = oracle.symgs_adjoint(inputs.standard_normal(17, shape),
+                                   direction, kind="var7",
+                                   faces=(pr["kx"], pr["ky"], pr["kz"]))
+    gr, gx = m.symgs_adjoint(A, dev(inputs.standard_normal(17, shape)),
+                             direction)
+    assert rel_inf(host(gr), ref[0]) <= 1e-13
+    assert rel_inf(host(gx), ref[1]) <= 1e-13
 
 
 @pytest.mark.parametrize("kind", ["const27", "var7"])

@@ -117,3 +117,40 @@ def test_degenerate_single_point():
     r = np.array([[[13.0]]])
     assert oracle.symgs27(r, np.zeros_like(r), "fwd")[0, 0, 0] == 0.5
     assert oracle.spmv27(r)[0, 0, 0] == 26 * 13.0
+
+
+def _dense_sweep_adjoint(A, g, direction):
+    """(gr, gx) of <g, S(r, x)> from the dense triangles of an assembled A:
+    forward S = (D+L)^{-1}(r - U x), backward S = (D+U)^{-1}(r - L x), sym =
+    backward after forward; transposed solves written out with
+    solve_triangular(trans=1), no symmetry assumed."""
+    DL, DU = np.tril(A), np.triu(A)
+    U, L = np.triu(A, 1), np.tril(A, -1)
+    if direction == "fwd":
+        gr = sla.solve_triangular(DL, g, lower=True, trans=1)
+        return gr, -U.T @ gr
+    if direction == "bwd":
+        gr = sla.solve_triangular(DU, g, lower=False, trans=1)
+        return gr, -L.T @ gr
+    grb, gmid = _dense_sweep_adjoint(A, g, "bwd")
+    grf, gx = _dense_sweep_adjoint(A, gmid, "fwd")
+    return grb + grf, gx
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 5), (6, 6, 6), (1, 2, 7)])
+@pytest.mark.parametrize("direction", ["fwd", "bwd", "sym"])
+def test_sweep_adjoint_vs_dense_transposed_solves(shape, direction):
+    nz, ny, nx = shape
+    A = assemble.const27(nx, ny, nz).toarray()
+    g = inputs.standard_normal(7, shape)
+    gr, gx = oracle.symgs_adjoint(g, direction)
+    rr, rx = _dense_sweep_adjoint(A, g.ravel(), direction)
+    assert np.max(np.abs(gr.ravel() - rr)) <= 1e-13 * np.max(np.abs(rr))
+    assert np.max(np.abs(gx.ravel() - rx)) <= 1e-13 * np.max(np.abs(rx))
+    # and the defining identity <g, S(r, x)> = <gr, r> + <gx, x> (S affine
+    # in (r, x) with S(0, 0) = 0)
+    r = inputs.standard_normal(8, shape)
+    x = inputs.standard_normal(9, shape)
+    lhs = np.dot(g.ravel(), oracle.symgs27(r, x, direction).ravel())
+    rhs = np.dot(gr.ravel(), r.ravel()) + np.dot(gx.ravel(), x.ravel())
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))

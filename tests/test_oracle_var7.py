@@ -73,26 +73,83 @@ def test_sweeps_are_triangular_solves(shape):
                                x0.ravel(), lower=False)
     assert np.max(np.abs(xb.ravel() - ref)) <= 1e-13 * np.max(np.abs(ref))
     lo = oracle.spmv_var7_part(x0, kx, ky, kz, -1).ravel()
-    assert np.allclose(lo, np.tril(A, -1) @ x0.ravel(), atol=1e-13)
+    assert np.allclose(lo, np.tril(A, -1) @ x0.ravel(), rtol=0, atol=1e-13)
+    up = oracle.spmv_var7_part(x0, kx, ky, kz, +1).ravel()
+    assert np.allclose(up, np.triu(A, 1) @ x0.ravel(), rtol=0, atol=1e-13)
+    assert np.allclose(lo + up + np.diag(A) * x0.ravel(), A @ x0.ravel(),
+                       rtol=0, atol=1e-12)
 
 
-def test_coarsen_constant_and_spd():
-    # Reading (the paper is silent): coarse face = series combination of the
-    # two fine faces it spans, over the doubled spacing.  For unit faces this
-    # is 1/4 everywhere; the coarse operator stays SPD.
-    shape = (4, 4, 4)
+def _schur_conductances(k):
+    """Face conductances of the exact coarse operator on a 1-D line: the
+    fine operator D^T K D (Sec. 4.1, assembled through the paper's D and P
+    matrices) with faces k[0..n], the odd points eliminated (Schur
+    complement onto the even points, which injection keeps).  Returns the
+    n/2 + 1 conductances: the coupling between consecutive coarse points,
+    and at each end the row sum, i.e. the coupling to the Dirichlet ghost."""
+    n = len(k) - 1
+    D = assemble.padded_diff(n).toarray()
+    A = D.T @ np.diag(k) @ D
+    ev, od = np.arange(0, n, 2), np.arange(1, n, 2)
+    S = (A[np.ix_(ev, ev)] - A[np.ix_(ev, od)] @
+         np.linalg.solve(A[np.ix_(od, od)], A[np.ix_(od, ev)]))
+    m = len(ev)
+    if m == 1:  # one coarse point touches both ghosts: only the total
+        return S[0, 0]
+    c = np.empty(m + 1)
+    c[0] = S[0].sum()
+    c[1:m] = -np.diag(S, 1)
+    c[m] = S[m - 1].sum()
+    return c
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("n", [2, 8, 14])
+def test_coarsen_is_half_the_exact_1d_elimination(axis, n):
+    # Reading (the paper is silent): every coarse face gets one constant
+    # multiple (1/2) of the conductance that exact elimination of the fine
+    # points between coarse points gives on a line.  A planted factor on
+    # one face, e.g. the first, breaks the constant ratio.
+    ext = [2, 2, 2]
+    ext[axis] = n
+    shape = (ext[2], ext[1], ext[0])
+    pr = _problem(shape, seed=40 + n + axis)
+    kc = oracle.var7_coarsen(pr["kx"], pr["ky"], pr["kz"])[axis]
+    # the fine line through the coincident points (2J, 2K) = (0, 0) and the
+    # coarse faces on it
+    if axis == 0:
+        line, cline = pr["kx"][0, 0, :], kc[0, 0, :]
+    elif axis == 1:
+        line, cline = pr["ky"][0, :, 0], kc[0, :, 0]
+    else:
+        line, cline = pr["kz"][:, 0, 0], kc[:, 0, 0]
+    exact = _schur_conductances(line)
+    if n == 2:
+        # one coarse point: its two faces together against the total
+        assert np.isclose(cline.sum() / exact, 0.5, rtol=1e-13, atol=0)
+        return
+    ratio = cline / exact
+    assert np.allclose(ratio, 0.5, rtol=1e-13, atol=0), ratio
+
+
+def test_coarsen_unit_faces_and_spd():
+    # unit faces: the first face of each axis spans one fine face (1/2), the
+    # others two in series (1/2 * 1/2); the coarse operator stays SPD
     one = lambda s: np.ones(s)  # noqa: E731
     kxc, kyc, kzc = oracle.var7_coarsen(one((4, 4, 5)), one((4, 5, 4)),
                                         one((5, 4, 4)))
-    for a in (kxc, kyc, kzc):
-        assert np.all(a == 0.25)
+    assert np.all(kxc[:, :, 0] == 0.5) and np.all(kxc[:, :, 1:] == 0.25)
+    assert np.all(kyc[:, 0, :] == 0.5) and np.all(kyc[:, 1:, :] == 0.25)
+    assert np.all(kzc[0] == 0.5) and np.all(kzc[1:] == 0.25)
     pr = _problem((8, 6, 4), seed=3)
     c = oracle.var7_coarsen(pr["kx"], pr["ky"], pr["kz"])
     assert c[0].shape == (4, 3, 3) and c[1].shape == (4, 4, 2) and \
         c[2].shape == (5, 3, 2)
     Ac = assemble.var7(*c).toarray()
+    assert np.allclose(Ac, Ac.T, atol=0)
     assert np.linalg.eigvalsh(Ac).min() > 0
-    # series combination of two faces a, b over doubled spacing: ab/(2(a+b))
+    # transverse position: coarse (I, J, K) = (1, 2, 1) takes the fine row
+    # (2J, 2K) = (4, 2)
     kx = pr["kx"]
     a, b = kx[2, 4, 1], kx[2, 4, 2]
     assert np.isclose(c[0][1, 2, 1], a * b / (2 * (a + b)), rtol=1e-15)
@@ -138,6 +195,20 @@ def test_face_gradient_vs_finite_differences():
     fd = (_loss_and_grads_dense(kx, ky, kz, fp, ut)[3] -
           _loss_and_grads_dense(kx, ky, kz, fm, ut)[3]) / (2 * h)
     assert abs(fd - lam[i]) <= 1e-6 * max(1, abs(fd))
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 5), (6, 6, 6), (1, 1, 6)])
+@pytest.mark.parametrize("direction", ["fwd", "bwd", "sym"])
+def test_sweep_adjoint_vs_dense_transposed_solves(shape, direction):
+    from tests.test_oracle_const27 import _dense_sweep_adjoint
+    pr = _problem(shape, seed=31)
+    f = (pr["kx"], pr["ky"], pr["kz"])
+    A = assemble.var7(*f).toarray()
+    g = inputs.standard_normal(7, shape)
+    gr, gx = oracle.symgs_adjoint(g, direction, kind="var7", faces=f)
+    rr, rx = _dense_sweep_adjoint(A, g.ravel(), direction)
+    assert np.max(np.abs(gr.ravel() - rr)) <= 1e-13 * np.max(np.abs(rr))
+    assert np.max(np.abs(gx.ravel() - rx)) <= 1e-13 * np.max(np.abs(rx))
 
 
 def test_sweep_adjoint_dot_products():
