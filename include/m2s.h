@@ -262,8 +262,17 @@ void m2s_mg_destroy(m2s_mg *mg);
  * back for the convergence and breakdown tests, except in a fixed-iteration
  * run (rtol <= 0) without history or residual replacement: there the host
  * does not wait per iteration, a breakdown (p.Ap <= 0 or a non-finite
- * scalar) is latched on the device and reported after the last iteration,
- * and iters is then max_iter.
+ * scalar) is latched on the device and reported after the last iteration.
+ * Either way a breakdown leaves x at the last iterate before the failing
+ * update (from that iteration on the update kernels leave x, r and p
+ * alone) and iters is the iteration that broke down.
+ * m2s_pcg_solve allocates its CG vectors (and, for SYMGS, a sweep
+ * workspace) on every call and frees them before returning;
+ * m2s_pcg_solve_ws takes them from a workspace made once with
+ * m2s_pcg_workspace_create for an operator of the same kind and extent, and
+ * allocates nothing (M2S_ERR_SHAPE for another kind or extent, M2S_ERR_ALIAS
+ * if b or x is one of its vectors).  One workspace serves one solve at a
+ * time; m2s_pcg_workspace_destroy synchronises the device first.
  * --------------------------------------------------------------------- */
 typedef enum {
     M2S_PC_NONE = 0,
@@ -292,6 +301,16 @@ m2s_status m2s_pcg_solve(const m2s_stencil *A, m2s_precond precond,
                          double *hist /* host, max_iter+1 or NULL */,
                          hipStream_t stream);
 
+typedef struct m2s_pcg_workspace m2s_pcg_workspace;
+m2s_status m2s_pcg_workspace_create(const m2s_stencil *A,
+                                    m2s_pcg_workspace **out);
+void m2s_pcg_workspace_destroy(m2s_pcg_workspace *ws);
+m2s_status m2s_pcg_solve_ws(const m2s_stencil *A, m2s_precond precond,
+                            m2s_mg *mg, const double *b, double *x,
+                            const m2s_pcg_opts *opts, m2s_pcg_info *info,
+                            double *hist, m2s_pcg_workspace *ws,
+                            hipStream_t stream);
+
 /* ---------------------------------------------------------------------
  * Gradient with respect to the VAR7 face coefficients of a loss whose
  * derivative with respect to the solution u of A(k) u = f has adjoint
@@ -316,12 +335,49 @@ m2s_status m2s_convert(const void *src, m2s_dtype src_t, void *dst,
                        m2s_dtype dst_t, int64_t n, hipStream_t stream);
 
 /* ---------------------------------------------------------------------
- * ILU of the 27-point operator (the ILU microbenchmark of Sec. 7.2.1),
- * CONST27 F64: M = (D + L) D^{-1} (D + U) with L, U the strict lower and
+ * Reference streaming passes for measurement (not a step of the method):
+ * kind 0 copies c = a, kind 1 is the STREAM triad c = a + s*b, over n
+ * doubles (device, 16-byte aligned; c must not overlap a or b).  They give
+ * the HBM rate a plain streaming kernel reaches (bytes moved: 16 n for the
+ * copy, 24 n for the triad), against which the sweeps' rates are also
+ * reported.  M2S_ERR_ARG for another kind, a null or misaligned pointer or
+ * n < 0; M2S_ERR_ALIAS for overlap.
+ * --------------------------------------------------------------------- */
+m2s_status m2s_stream(int32_t kind, const double *a, const double *b,
+                      double *c, double s, int64_t n, hipStream_t stream);
+
+/* ---------------------------------------------------------------------
+ * ILU(0) of the 27-point operator (the incomplete LU of the ILU
+ * microbenchmark, Sec. 7.2.1, as the paper cites it, Sec. 9), CONST27 F64:
+ * L unit lower and U upper triangular with the sparsity pattern of A, by
+ * row-wise (IKJ) Gaussian elimination in lexicographic order with every
+ * fill-in outside the pattern dropped, so that (L U)_pq = a_pq on the
+ * pattern.  Factor arrays per point p (C order of nz, ny, nx): L[13 p + a]
+ * = l_pq for the 13 lower offsets, U[14 p] = u_pp and U[14 p + 1 + b] =
+ * u_pq for the 13 upper offsets, offsets in lexicographic (dk, dj, di)
+ * order, 0 outside the grid (caller-owned device arrays of 13 n and 14 n
+ * doubles).  m2s_ilu0_apply computes z = (L U)^{-1} r: the lower solve
+ * (p ascending), then the upper solve in place on z (p descending).  Both
+ * run hyperplane by hyperplane (T = i + 2j + 4k, one launch per step), so
+ * a call queues 7n - 6 (factor) or 2(7n - 6) (apply) launches for n^3.
+ * M2S_ERR_UNSUPPORTED for other kinds, M2S_ERR_DTYPE for F32,
+ * M2S_ERR_ALIAS if L and U overlap or z overlaps r, L or U.
+ * --------------------------------------------------------------------- */
+m2s_status m2s_ilu0_factor(const m2s_stencil *A, double *L, double *U,
+                           hipStream_t stream);
+m2s_status m2s_ilu0_apply(const m2s_stencil *A, const double *L,
+                          const double *U, const double *r, double *z,
+                          hipStream_t stream);
+
+/* ---------------------------------------------------------------------
+ * D-ILU of the 27-point operator (the factored-diagonal incomplete
+ * factorisation: A's off-diagonals kept, only the diagonal factored; not
+ * ILU(0), see above), CONST27 F64: M = (D + L) D^{-1} (D + U) with L, U the
+ * strict lower and
  * upper parts of A and the diagonal D = diag(d) factored so that
  * diag(M) = diag(A):  d_p = diag - sum_{q lower} off^2 / d_q.
- * m2s_ilu27_factor writes w = 1/d (n doubles, caller-owned).
- * m2s_ilu27_apply computes z = M^{-1} r: the lower solve
+ * m2s_dilu27_factor writes w = 1/d (n doubles, caller-owned).
+ * m2s_dilu27_apply computes z = M^{-1} r: the lower solve
  *   y_p = (r_p - off sum_{q lower} y_q) / d_p,  p ascending,
  * into the workspace's scratch vector, then the upper solve
  *   z_p = y_p - off (sum_{q upper} z_q) / d_p,  p descending.
@@ -329,9 +385,9 @@ m2s_status m2s_convert(const void *src, m2s_dtype src_t, void *dst,
  * sweep order, run on the 27-point wavefront tiles (1 or 2 compute
  * wavefronts per tile, M2S_ERR_HIP otherwise).  r, w, z must not overlap.
  * --------------------------------------------------------------------- */
-m2s_status m2s_ilu27_factor(const m2s_stencil *A, void *w, m2s_workspace *ws,
+m2s_status m2s_dilu27_factor(const m2s_stencil *A, void *w, m2s_workspace *ws,
                             hipStream_t stream);
-m2s_status m2s_ilu27_apply(const m2s_stencil *A, const void *w,
+m2s_status m2s_dilu27_apply(const m2s_stencil *A, const void *w,
                            const void *r, void *z, m2s_workspace *ws,
                            hipStream_t stream);
 

@@ -76,8 +76,11 @@ def _load():
             dtype=np.int32, flags="C_CONTIGUOUS")]
         g("lu5_factor").restype = i
         g("jacobi9").argtypes = [i, i, R, R, P, P, i, P]
-        g("ilu27_factor").argtypes = [i, i, i, R, R, P]
-        g("ilu27_solve").argtypes = [i, i, i, R, P, P, P]
+        g("dilu27_factor").argtypes = [i, i, i, R, R, P]
+        g("dilu27_solve").argtypes = [i, i, i, R, P, P, P]
+        g("ilu0_27_factor").argtypes = [i, i, i, R, R, P, P]
+        g("ilu0_27_factor").restype = i
+        g("ilu0_27_solve").argtypes = [i, i, i, P, P, P, P]
         g("penta_lines").argtypes = [i, i, i, i, P, P, P]
         g("bt_lines").argtypes = [i, i, i, i, P, P, P]
         g("bt_lines").restype = i
@@ -347,20 +350,43 @@ def jacobi9(b, x0, iters, diag=8.0, off=-1.0, dtype=np.float64):
     return x
 
 
-def ilu27_factor(shape, diag=26.0, off=-1.0, dtype=np.float64):
+def dilu27_factor(shape, diag=26.0, off=-1.0, dtype=np.float64):
     """Factor diagonal d of the 27-point ILU M = (D + L) D^{-1} (D + U)."""
     nz, ny, nx = shape
     d = np.empty(shape, dtype=dtype)
-    _fn("ilu27_factor", dtype)(nx, ny, nz, diag, off, d)
+    _fn("dilu27_factor", dtype)(nx, ny, nz, diag, off, d)
     return d
 
 
-def ilu27_solve(d, r, off=-1.0, dtype=np.float64):
+def dilu27_solve(d, r, off=-1.0, dtype=np.float64):
     """z = M^{-1} r (lower solve p ascending, then upper solve p descending)."""
     d, r = _c(d, dtype), _c(r, dtype)
     nz, ny, nx = r.shape
     z = np.empty_like(r)
-    _fn("ilu27_solve", dtype)(nx, ny, nz, off, d, r, z)
+    _fn("dilu27_solve", dtype)(nx, ny, nz, off, d, r, z)
+    return z
+
+
+def ilu0_27_factor(shape, diag=26.0, off=-1.0, dtype=np.float64):
+    """ILU(0) of the 27-point operator: (L, U) with L of shape shape + (13,)
+    (the lower offsets' l_pq, unit diagonal implied) and U of shape
+    shape + (14,) (the pivot u_pp, then the upper offsets' u_pq), offsets in
+    lexicographic (dk, dj, di) order, 0 outside the grid."""
+    nz, ny, nx = shape
+    Lf = np.zeros(shape + (13,), dtype=dtype)
+    Uf = np.zeros(shape + (14,), dtype=dtype)
+    if _fn("ilu0_27_factor", dtype)(nx, ny, nz, diag, off, Lf, Uf) != 0:
+        raise ZeroDivisionError("ILU(0): zero pivot")
+    return Lf, Uf
+
+
+def ilu0_27_solve(Lf, Uf, r, dtype=np.float64):
+    """z = (L U)^{-1} r: lower solve p ascending, upper solve p
+    descending."""
+    Lf, Uf, r = _c(Lf, dtype), _c(Uf, dtype), _c(r, dtype)
+    nz, ny, nx = r.shape
+    z = np.empty_like(r)
+    _fn("ilu0_27_solve", dtype)(nx, ny, nz, Lf, Uf, r, z)
     return z
 
 

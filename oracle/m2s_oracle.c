@@ -10,8 +10,8 @@
  *
  * Parity status of each part is recorded by the tests under tests/ that pin
  * it (assembled sparse matrices, triangular solves, closed forms, symmetry,
- * finite differences).  Parity unpinned: the VAR7 coarse-coefficient rule
- * (a reading; only symmetry and convergence of the resulting V-cycle pin it).
+ * finite differences, exact elimination on a line for the VAR7 coarse
+ * faces).  No routine is left unpinned.
  */
 #include <math.h>
 #include <stdlib.h>

@@ -83,6 +83,11 @@ _SIGS = {
     "m2s_pcg_solve": (C.c_int, [_S, C.c_int, _P, _P, _P,
                                 C.POINTER(PcgOpts), C.POINTER(PcgInfo), _P,
                                 _P]),
+    "m2s_pcg_workspace_create": (C.c_int, [_S, C.POINTER(C.c_void_p)]),
+    "m2s_pcg_workspace_destroy": (None, [_P]),
+    "m2s_pcg_solve_ws": (C.c_int, [_S, C.c_int, _P, _P, _P,
+                                   C.POINTER(PcgOpts), C.POINTER(PcgInfo),
+                                   _P, _P, _P]),
     "m2s_face_grad": (C.c_int, [_S, _P, _P, _P, _P, _P, _P]),
     "m2s_jacobi9": (C.c_int, [C.c_int32, C.c_int32, C.c_double, C.c_double,
                               _P, _P, _P, C.c_int32, C.c_int32, _P]),
@@ -90,10 +95,14 @@ _SIGS = {
                                   _P, _P, _P, _P, _P]),
     "m2s_bt_lines": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                _P, _P, _P, _P, _P]),
-    "m2s_ilu27_factor": (C.c_int, [_S, _P, _P, _P]),
-    "m2s_ilu27_apply": (C.c_int, [_S, _P, _P, _P, _P, _P]),
+    "m2s_dilu27_factor": (C.c_int, [_S, _P, _P, _P]),
+    "m2s_dilu27_apply": (C.c_int, [_S, _P, _P, _P, _P, _P]),
+    "m2s_ilu0_factor": (C.c_int, [_S, _P, _P, _P]),
+    "m2s_ilu0_apply": (C.c_int, [_S, _P, _P, _P, _P, _P]),
     "m2s_dot": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
     "m2s_convert": (C.c_int, [_P, C.c_int, _P, C.c_int, C.c_int64, _P]),
+    "m2s_stream": (C.c_int, [C.c_int32, _P, _P, _P, C.c_double, C.c_int64,
+                             _P]),
     "m2s_plan_sweep": (C.c_int, [_S, C.POINTER(SweepPlanC)]),
 }
 

@@ -280,10 +280,36 @@ class MG:
             self._h = None
 
 
+class PcgWorkspace:
+    """The CG vectors and scalars of one operator (m2s_pcg_workspace), made
+    once so that solves with it allocate nothing."""
+
+    def __init__(self, A: Stencil):
+        lib = L.load()
+        self.A = A
+        h = C.c_void_p()
+        L.check(lib.m2s_pcg_workspace_create(A.ref(), C.byref(h)),
+                "m2s_pcg_workspace_create")
+        self._h = h
+        self._destroy = lib.m2s_pcg_workspace_destroy
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._destroy(h)
+            self._h = None
+
+
 def pcg_solve(A: Stencil, b, x=None, precond="mg", mg: MG | None = None,
               max_iter=50, rtol=0.0, replace_every=0, history=False,
-              raise_on_error=True):
-    """HPCG-form PCG; returns (x, info dict)."""
+              raise_on_error=True, ws: PcgWorkspace | None = None):
+    """HPCG-form PCG; returns (x, info dict).  With a PcgWorkspace the solve
+    allocates nothing (m2s_pcg_solve_ws); without one the library allocates
+    and frees the CG vectors inside the call (m2s_pcg_solve)."""
     lib = L.load()
     _need(b, torch.float64, A.shape, "b")
     if x is None:
@@ -293,10 +319,15 @@ def pcg_solve(A: Stencil, b, x=None, precond="mg", mg: MG | None = None,
     opts = L.PcgOpts(int(max_iter), float(rtol), int(replace_every))
     info = L.PcgInfo()
     hist = np.zeros(max_iter + 1) if history else None
-    st = lib.m2s_pcg_solve(A.ref(), pc, mg.handle if mg else None, _ptr(b),
-                           _ptr(x), C.byref(opts), C.byref(info),
-                           hist.ctypes.data_as(C.c_void_p) if history
-                           else None, _stream())
+    hp = hist.ctypes.data_as(C.c_void_p) if history else None
+    if ws is not None:
+        st = lib.m2s_pcg_solve_ws(A.ref(), pc, mg.handle if mg else None,
+                                  _ptr(b), _ptr(x), C.byref(opts),
+                                  C.byref(info), hp, ws.handle, _stream())
+    else:
+        st = lib.m2s_pcg_solve(A.ref(), pc, mg.handle if mg else None,
+                               _ptr(b), _ptr(x), C.byref(opts),
+                               C.byref(info), hp, _stream())
     out = dict(status=L.STATUS.get(st, st), iters=info.iters,
                rel_res=info.rel_res, true_rel_res=info.true_rel_res,
                r0_norm=info.r0_norm, seconds=info.seconds)
@@ -325,17 +356,18 @@ def jacobi9(b, x, iters, tblock=8, diag=8.0, off=-1.0, tmp=None):
     return x
 
 
-def ilu27_factor(A: Stencil, ws: Workspace | None = None):
-    """w = 1/d, the factor of the 27-point ILU M = (D+L) D^-1 (D+U)."""
+def dilu27_factor(A: Stencil, ws: Workspace | None = None):
+    """w = 1/d, the factor of the 27-point D-ILU M = (D+L) D^-1 (D+U) (the
+    factored-diagonal variant; ILU(0) is ilu0_factor)."""
     lib = L.load()
     w = torch.empty(A.field_shape, dtype=A.dtype, device="cuda")
     ws = ws or Workspace(A)
-    L.check(lib.m2s_ilu27_factor(A.ref(), _ptr(w), ws.handle, _stream()),
-            "m2s_ilu27_factor")
+    L.check(lib.m2s_dilu27_factor(A.ref(), _ptr(w), ws.handle, _stream()),
+            "m2s_dilu27_factor")
     return w
 
 
-def ilu27_apply(A: Stencil, w, r, z=None, ws: Workspace | None = None):
+def dilu27_apply(A: Stencil, w, r, z=None, ws: Workspace | None = None):
     """z = M^-1 r (lower, then upper triangular sweep)."""
     lib = L.load()
     _need(w, A.dtype, A.field_shape, "w")
@@ -344,8 +376,37 @@ def ilu27_apply(A: Stencil, w, r, z=None, ws: Workspace | None = None):
         z = torch.empty_like(r)
     _need(z, A.dtype, A.field_shape, "z")
     ws = ws or Workspace(A)
-    L.check(lib.m2s_ilu27_apply(A.ref(), _ptr(w), _ptr(r), _ptr(z),
-                                ws.handle, _stream()), "m2s_ilu27_apply")
+    L.check(lib.m2s_dilu27_apply(A.ref(), _ptr(w), _ptr(r), _ptr(z),
+                                ws.handle, _stream()), "m2s_dilu27_apply")
+    return z
+
+
+def ilu0_factor(A: Stencil):
+    """ILU(0) of the 27-point operator: (L, U) with L of shape
+    field_shape + (13,) (the lower offsets' l_pq) and U of shape
+    field_shape + (14,) (u_pp, then the upper offsets' u_pq), offsets in
+    lexicographic (dk, dj, di) order."""
+    lib = L.load()
+    if A.dtype != torch.float64:
+        raise TypeError("ilu0_factor takes an F64 operator")
+    Lf = torch.empty(A.field_shape + (13,), dtype=A.dtype, device="cuda")
+    Uf = torch.empty(A.field_shape + (14,), dtype=A.dtype, device="cuda")
+    L.check(lib.m2s_ilu0_factor(A.ref(), _ptr(Lf), _ptr(Uf), _stream()),
+            "m2s_ilu0_factor")
+    return Lf, Uf
+
+
+def ilu0_apply(A: Stencil, Lf, Uf, r, z=None):
+    """z = (L U)^{-1} r (lower, then upper triangular solve)."""
+    lib = L.load()
+    _need(Lf, A.dtype, A.field_shape + (13,), "L")
+    _need(Uf, A.dtype, A.field_shape + (14,), "U")
+    _need(r, A.dtype, A.field_shape, "r")
+    if z is None:
+        z = torch.empty_like(r)
+    _need(z, A.dtype, A.field_shape, "z")
+    L.check(lib.m2s_ilu0_apply(A.ref(), _ptr(Lf), _ptr(Uf), _ptr(r),
+                               _ptr(z), _stream()), "m2s_ilu0_apply")
     return z
 
 
@@ -440,6 +501,21 @@ def convert(src, dtype):
     return dst
 
 
+def stream(kind, a, c, b=None, s=1.0):
+    """STREAM reference pass (measurement only): "copy" c = a, "triad"
+    c = a + s b, over double tensors."""
+    lib = L.load()
+    k = {"copy": 0, "triad": 1}[kind]
+    n = a.numel()
+    _need(a, torch.float64, tuple(a.shape), "a")
+    _need(c, torch.float64, tuple(a.shape), "c")
+    if k == 1:
+        _need(b, torch.float64, tuple(a.shape), "b")
+    L.check(lib.m2s_stream(k, _ptr(a), _ptr(b) if b is not None else None,
+                           _ptr(c), float(s), n, _stream()), "m2s_stream")
+    return c
+
+
 def plan_sweep(A: Stencil):
     """Host-only schedule of the wavefront sweep (no GPU needed)."""
     lib = L.load()
@@ -460,22 +536,27 @@ class SolveFn(torch.autograd.Function):
     def forward(ctx, kx, ky, kz, f, levels, rtol, max_iter):
         A = var7(kx, ky, kz)
         mg = MG(A, levels)
+        pws = PcgWorkspace(A)
         u, info = pcg_solve(A, f.contiguous(), None, "mg", mg,
-                            max_iter=max_iter, rtol=rtol)
+                            max_iter=max_iter, rtol=rtol, ws=pws)
         ctx.save_for_backward(kx, ky, kz, u)
         ctx.cfg = (levels, rtol, max_iter)
         ctx.info = info
+        # the backward solves with the same operator: it reuses the
+        # hierarchy and the CG vectors (autograd rejects a backward after an
+        # in-place change of the saved faces, so they still describe it)
+        ctx.A, ctx.mg, ctx.pws = A, mg, pws
         return u
 
     @staticmethod
     def backward(ctx, gu):
         kx, ky, kz, u = ctx.saved_tensors
         levels, rtol, max_iter = ctx.cfg
-        A = var7(kx, ky, kz)
-        mg = MG(A, levels)
+        A, mg, pws = ctx.A, ctx.mg, ctx.pws
         lam, _ = pcg_solve(A, gu.contiguous(), None, "mg", mg,
-                           max_iter=max_iter, rtol=rtol)
+                           max_iter=max_iter, rtol=rtol, ws=pws)
         gx, gy, gz = face_grad(A, u, lam)
+        ctx.A = ctx.mg = ctx.pws = None
         return gx, gy, gz, lam, None, None, None
 
 

@@ -366,7 +366,9 @@ const char *m2s_status_string(m2s_status s)
     return "unknown status";
 }
 
-int m2s_version(void) { return 10100; }  // 1.1.0: m2s_bt_lines added
+// 2.0.0: m2s_ilu27_* renamed m2s_dilu27_*; m2s_ilu0_*, the PCG workspace
+// entry points and m2s_stream added
+int m2s_version(void) { return 20000; }
 
 m2s_status m2s_plan_sweep(const m2s_stencil *A, m2s_sweep_plan *plan)
 {
@@ -684,7 +686,7 @@ m2s_status m2s_ssor_sweep_sequential(const m2s_stencil *A, const void *b,
 }
 
 namespace {
-m2s_status ilu27_prepare(const m2s_stencil *A, m2s_workspace *ws,
+m2s_status dilu27_prepare(const m2s_stencil *A, m2s_workspace *ws,
                          SweepPlan &P)
 {
     m2s_status st = validate(A);
@@ -697,29 +699,60 @@ m2s_status ilu27_prepare(const m2s_stencil *A, m2s_workspace *ws,
 }
 }  // namespace
 
-m2s_status m2s_ilu27_factor(const m2s_stencil *A, void *w, m2s_workspace *ws,
+m2s_status m2s_dilu27_factor(const m2s_stencil *A, void *w, m2s_workspace *ws,
                             hipStream_t stream)
 {
     if (!w) return M2S_ERR_ARG;
     SweepPlan P{};
-    m2s_status st = ilu27_prepare(A, ws, P);
+    m2s_status st = dilu27_prepare(A, ws, P);
     if (st != M2S_OK) return st;
-    return hip_status(launch_ilu27(*A, 1, nullptr, nullptr, w, *ws, P, stream));
+    return hip_status(launch_dilu27(*A, 1, nullptr, nullptr, w, *ws, P, stream));
 }
 
-m2s_status m2s_ilu27_apply(const m2s_stencil *A, const void *w,
+m2s_status m2s_dilu27_apply(const m2s_stencil *A, const void *w,
                            const void *r, void *z, m2s_workspace *ws,
                            hipStream_t stream)
 {
     if (!w || !r || !z) return M2S_ERR_ARG;
     SweepPlan P{};
-    m2s_status st = ilu27_prepare(A, ws, P);
+    m2s_status st = dilu27_prepare(A, ws, P);
     if (st != M2S_OK) return st;
     const size_t vb = (size_t)npoints(*A) * elem_size(*A);
     if (overlap(w, r, vb) || overlap(w, z, vb) || overlap(r, z, vb))
         return M2S_ERR_ALIAS;
-    M2S_TRY(launch_ilu27(*A, 2, r, w, ws->scratch, *ws, P, stream));
-    return hip_status(launch_ilu27(*A, 3, ws->scratch, w, z, *ws, P, stream));
+    M2S_TRY(launch_dilu27(*A, 2, r, w, ws->scratch, *ws, P, stream));
+    return hip_status(launch_dilu27(*A, 3, ws->scratch, w, z, *ws, P, stream));
+}
+
+m2s_status m2s_ilu0_factor(const m2s_stencil *A, double *L, double *U,
+                           hipStream_t stream)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (A->kind != M2S_CONST27) return M2S_ERR_UNSUPPORTED;
+    if (A->dtype != M2S_F64) return M2S_ERR_DTYPE;
+    if (!L || !U) return M2S_ERR_ARG;
+    const int64_t n = npoints(*A);
+    if (overlap2(L, (size_t)(13 * n) * 8, U, (size_t)(14 * n) * 8))
+        return M2S_ERR_ALIAS;
+    return hip_status(launch_ilu0_factor(*A, L, U, stream));
+}
+
+m2s_status m2s_ilu0_apply(const m2s_stencil *A, const double *L,
+                          const double *U, const double *r, double *z,
+                          hipStream_t stream)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (A->kind != M2S_CONST27) return M2S_ERR_UNSUPPORTED;
+    if (A->dtype != M2S_F64) return M2S_ERR_DTYPE;
+    if (!L || !U || !r || !z) return M2S_ERR_ARG;
+    const int64_t n = npoints(*A);
+    const size_t vb = 8 * (size_t)n;
+    if (overlap(r, z, vb) || overlap2(L, (size_t)(13 * n) * 8, z, vb) ||
+        overlap2(U, (size_t)(14 * n) * 8, z, vb))
+        return M2S_ERR_ALIAS;
+    return hip_status(launch_ilu0_apply(*A, L, U, r, z, stream));
 }
 
 m2s_status m2s_penta_lines(int32_t nx, int32_t ny, int32_t nz, int32_t axis,
@@ -803,6 +836,24 @@ m2s_status m2s_dot(const double *x, const double *y, int64_t n, double *out,
     if (e == hipSuccess) e = launch_dot(x, y, n, partials, out, stream);
     hipError_t f = hipFreeAsync(partials, stream);
     return (e == hipSuccess && f == hipSuccess) ? M2S_OK : M2S_ERR_HIP;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+m2s_status m2s_stream(int32_t kind, const double *a, const double *b,
+                      double *c, double s, int64_t n, hipStream_t stream)
+{
+    if (kind != 0 && kind != 1) return M2S_ERR_ARG;
+    if (!a || !c || (kind == 1 && !b) || n < 0) return M2S_ERR_ARG;
+    auto mis = [](const void *p) { return ((uintptr_t)p & 15) != 0; };
+    if (mis(a) || mis(c) || (kind == 1 && mis(b))) return M2S_ERR_ARG;
+    const size_t vb = 8 * (size_t)n;
+    if (overlap(a, c, vb) || (kind == 1 && overlap(b, c, vb)))
+        return M2S_ERR_ALIAS;
+    if (n == 0) return M2S_OK;
+    return hip_status(launch_stream(kind, a, b, c, s, n, stream));
 }
 
 m2s_status m2s_convert(const void *src, m2s_dtype src_t, void *dst,
@@ -980,22 +1031,19 @@ m2s_status m2s_mg_vcycle(m2s_mg *mg, const double *r, double *z,
 // ------------------------------------------------------------------------
 namespace {
 
-struct PcgBuffers {
+}  // namespace
+
+// The PCG vectors and scalars of one operator, made once and reused by
+// every solve (m2s_pcg_solve_ws), so that a solve allocates nothing.
+struct m2s_pcg_workspace {
+    m2s_kind kind;
+    m2s_extent ext;
     double *r = nullptr, *z = nullptr, *p = nullptr, *ap = nullptr;
     double *sc = nullptr, *partials = nullptr;
-    m2s_workspace *ws = nullptr;
-    ~PcgBuffers()
-    {
-        (void)hipDeviceSynchronize();
-        if (r) (void)hipFree(r);
-        if (z) (void)hipFree(z);
-        if (p) (void)hipFree(p);
-        if (ap) (void)hipFree(ap);
-        if (sc) (void)hipFree(sc);
-        if (partials) (void)hipFree(partials);
-        if (ws) m2s_workspace_destroy(ws);
-    }
+    m2s_workspace *ws = nullptr;  // sweeps of the SYMGS preconditioner
 };
+
+namespace {
 
 m2s_status workspace_error(m2s_workspace *ws)
 {
@@ -1027,12 +1075,13 @@ m2s_status mg_error(m2s_mg *mg)
 
 }  // namespace
 
-extern "C" m2s_status m2s_pcg_solve(const m2s_stencil *A,
-                                    m2s_precond precond, m2s_mg *mg,
-                                    const double *b, double *x,
-                                    const m2s_pcg_opts *opts,
-                                    m2s_pcg_info *info, double *hist,
-                                    hipStream_t stream)
+extern "C" m2s_status m2s_pcg_solve_ws(const m2s_stencil *A,
+                                       m2s_precond precond, m2s_mg *mg,
+                                       const double *b, double *x,
+                                       const m2s_pcg_opts *opts,
+                                       m2s_pcg_info *info, double *hist,
+                                       m2s_pcg_workspace *W,
+                                       hipStream_t stream)
 {
     auto t0 = std::chrono::steady_clock::now();
     m2s_status st = validate(A);
@@ -1051,24 +1100,19 @@ extern "C" m2s_status m2s_pcg_solve(const m2s_stencil *A,
             mg->L[0].A.kind != A->kind)
             return M2S_ERR_SHAPE;
     }
+    if (!W) return M2S_ERR_ARG;
+    if (W->kind != A->kind || W->ext.nx != A->ext.nx ||
+        W->ext.ny != A->ext.ny || W->ext.nz != A->ext.nz)
+        return M2S_ERR_SHAPE;
     const int64_t n = npoints(*A);
     const size_t vb = 8 * (size_t)n;
     if (overlap(b, x, vb)) return M2S_ERR_ALIAS;
-    PcgBuffers B;
-    if (hipMalloc((void **)&B.r, vb) != hipSuccess ||
-        hipMalloc((void **)&B.z, vb) != hipSuccess ||
-        hipMalloc((void **)&B.p, vb) != hipSuccess ||
-        hipMalloc((void **)&B.ap, vb) != hipSuccess ||
-        hipMalloc((void **)&B.sc, sizeof(double) * SC_N) != hipSuccess ||
-        hipMalloc((void **)&B.partials,
-                  sizeof(double) * dot_partials_capacity()) != hipSuccess)
-        return M2S_ERR_HIP;
+    // b and x must not be one of the workspace's own vectors
+    for (const double *v : {W->r, W->z, W->p, W->ap})
+        if (overlap(b, v, vb) || overlap(x, v, vb)) return M2S_ERR_ALIAS;
+    m2s_pcg_workspace &B = *W;
+    // the scalars start at zero (the partials' counter re-arms itself)
     M2S_TRY(hipMemsetAsync(B.sc, 0, sizeof(double) * SC_N, stream));
-    M2S_TRY(hipMemsetAsync(B.partials, 0,
-                           sizeof(double) * dot_partials_capacity(), stream));
-    if (precond == M2S_PC_SYMGS &&
-        (st = m2s_workspace_create(A, &B.ws)) != M2S_OK)
-        return st;
     double hsc[SC_N];
     auto fetch = [&]() -> m2s_status {
         if (hipMemcpyAsync(hsc, B.sc, sizeof(hsc), hipMemcpyDeviceToHost,
@@ -1119,7 +1163,7 @@ extern "C" m2s_status m2s_pcg_solve(const m2s_stencil *A,
             M2S_TRY(launch_spmv_dot(*A, B.p, B.ap, B.partials, B.sc + SC_PAP,
                                     stream));
             M2S_TRY(launch_update_xr(x, B.r, B.p, B.ap, n, B.sc, B.partials,
-                                     stream));
+                                     it, stream));
             // a fixed-iteration run without history or replacement has no
             // test to make before its last iteration: the scalars stay on
             // the device (a breakdown is latched there) and the host does
@@ -1130,6 +1174,9 @@ extern "C" m2s_status m2s_pcg_solve(const m2s_stencil *A,
             normr = std::sqrt(hsc[SC_RR]);
             if (hsc[SC_BD] != 0.0 || !(pap > 0.0) || !std::isfinite(pap) ||
                 !std::isfinite(normr) || !std::isfinite(hsc[SC_RZ])) {
+                // the update kernels leave x, r and p alone from the
+                // iteration that latched the breakdown on
+                if (hsc[SC_BD] != 0.0) it = (int)hsc[SC_BDIT];
                 result = M2S_ERR_BREAKDOWN;
                 break;
             }
@@ -1169,4 +1216,66 @@ extern "C" m2s_status m2s_pcg_solve(const m2s_stencil *A,
         info->seconds = std::chrono::duration<double>(t1 - t0).count();
     }
     return result;
+}
+
+extern "C" m2s_status m2s_pcg_workspace_create(const m2s_stencil *A,
+                                               m2s_pcg_workspace **out)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (!out) return M2S_ERR_ARG;
+    *out = nullptr;
+    if (A->kind == M2S_BLOCK7_5) return M2S_ERR_UNSUPPORTED;
+    if (A->dtype != M2S_F64) return M2S_ERR_DTYPE;
+    m2s_pcg_workspace *W = new (std::nothrow) m2s_pcg_workspace();
+    if (!W) return M2S_ERR_HIP;
+    W->kind = A->kind;
+    W->ext = A->ext;
+    const size_t vb = 8 * (size_t)npoints(*A);
+    const size_t pb = sizeof(double) * dot_partials_capacity();
+    bool ok = hipMalloc((void **)&W->r, vb) == hipSuccess &&
+              hipMalloc((void **)&W->z, vb) == hipSuccess &&
+              hipMalloc((void **)&W->p, vb) == hipSuccess &&
+              hipMalloc((void **)&W->ap, vb) == hipSuccess &&
+              hipMalloc((void **)&W->sc, sizeof(double) * SC_N) ==
+                  hipSuccess &&
+              hipMalloc((void **)&W->partials, pb) == hipSuccess &&
+              hipMemset(W->partials, 0, pb) == hipSuccess &&
+              hipDeviceSynchronize() == hipSuccess;
+    if (ok) ok = m2s_workspace_create(A, &W->ws) == M2S_OK;
+    if (!ok) {
+        m2s_pcg_workspace_destroy(W);
+        return M2S_ERR_HIP;
+    }
+    *out = W;
+    return M2S_OK;
+}
+
+extern "C" void m2s_pcg_workspace_destroy(m2s_pcg_workspace *W)
+{
+    if (!W) return;
+    (void)hipDeviceSynchronize();
+    for (double *v : {W->r, W->z, W->p, W->ap, W->sc, W->partials})
+        if (v) (void)hipFree(v);
+    if (W->ws) m2s_workspace_destroy(W->ws);
+    delete W;
+}
+
+extern "C" m2s_status m2s_pcg_solve(const m2s_stencil *A,
+                                    m2s_precond precond, m2s_mg *mg,
+                                    const double *b, double *x,
+                                    const m2s_pcg_opts *opts,
+                                    m2s_pcg_info *info, double *hist,
+                                    hipStream_t stream)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (A->kind == M2S_BLOCK7_5) return M2S_ERR_UNSUPPORTED;
+    if (A->dtype != M2S_F64) return M2S_ERR_DTYPE;
+    if (!b || !x || !opts) return M2S_ERR_ARG;
+    m2s_pcg_workspace *W = nullptr;
+    if ((st = m2s_pcg_workspace_create(A, &W)) != M2S_OK) return st;
+    st = m2s_pcg_solve_ws(A, precond, mg, b, x, opts, info, hist, W, stream);
+    m2s_pcg_workspace_destroy(W);
+    return st;
 }

@@ -525,6 +525,8 @@ __global__ void __launch_bounds__(256)
     update_p_kernel(const double *__restrict__ z, double *__restrict__ p,
                     int64_t n, const double *sc, int first)
 {
+    // SC_BD is written only by update_xr of an earlier iteration
+    if (sc[SC_BD] != 0.0) return;
     const double beta = first ? 0.0 : sc[SC_RZ] / sc[SC_RZ_OLD];
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x)
@@ -535,16 +537,22 @@ __global__ void __launch_bounds__(256)
     update_xr_kernel(double *__restrict__ x, double *__restrict__ r,
                      const double *__restrict__ p,
                      const double *__restrict__ ap, int64_t n, double *sc,
-                     double *partials, unsigned *counter)
+                     double *partials, unsigned *counter, int iter)
 {
     const double rz = sc[SC_RZ], pap = sc[SC_PAP];
     const double alpha = rz / pap;
-    if (blockIdx.x == 0 && threadIdx.x == 0 &&
-        (!(pap > 0.0) || !isfinite(pap) || !isfinite(rz)))
+    // every block computes `bad` from the same scalars; one latches it.  A
+    // block that already sees this launch's latch skips as well, since it
+    // then has bad set too
+    const bool bad = !(pap > 0.0) || !isfinite(pap) || !isfinite(rz);
+    const bool skip = bad || sc[SC_BD] != 0.0;
+    if (bad && blockIdx.x == 0 && threadIdx.x == 0 && sc[SC_BD] == 0.0) {
+        sc[SC_BDIT] = (double)iter;
         sc[SC_BD] = 1.0;
+    }
     double acc = 0.0;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-         q += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+         !skip && q < n; q += (int64_t)gridDim.x * blockDim.x) {
         x[q] = fma(alpha, p[q], x[q]);
         const double v = fma(-alpha, ap[q], r[q]);
         r[q] = v;
@@ -796,6 +804,54 @@ hipError_t launch_copy(void *dst, const void *src, int64_t bytes,
     return hipGetLastError();
 }
 
+// STREAM-style reference kernels (the measured HBM rate of a plain
+// streaming pass, beside the nominal peak): copy c = a, triad c = a + s b.
+// One 16-byte pair of doubles per thread, one wave of workgroups over the
+// whole array (measured on MI355X against 2, 4 and 8 pairs per thread and
+// non-temporal accesses: this plain form is the fastest, 6.2 / 6.0 TB/s
+// over 1 GiB arrays); thread 0 also takes an odd last element.
+template <int KIND>
+__global__ void __launch_bounds__(256)
+    stream_kernel(const double *__restrict__ a, const double *__restrict__ b,
+                  double *__restrict__ c, double sc, int64_t n)
+{
+    using d2 = __attribute__((ext_vector_type(2))) double;
+    const int64_t n2 = n / 2;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n2) {
+        const d2 x = ((const d2 *)a)[q];
+        if constexpr (KIND == 0) ((d2 *)c)[q] = x;
+        else ((d2 *)c)[q] = x + sc * ((const d2 *)b)[q];
+    }
+    if (q == 0 && (n & 1)) {
+        if constexpr (KIND == 0) c[n - 1] = a[n - 1];
+        else c[n - 1] = a[n - 1] + sc * b[n - 1];
+    }
+}
+
+hipError_t launch_stream(int kind, const double *a, const double *b,
+                         double *c, double sc, int64_t n, hipStream_t s)
+{
+    const int64_t nb = std::max<int64_t>(1, (n / 2 + 255) / 256);
+    if (nb >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    if (kind == 0)
+        hipLaunchKernelGGL(stream_kernel<0>, dim3((unsigned)nb), dim3(256), 0,
+                           s, a, b, c, sc, n);
+    else
+        hipLaunchKernelGGL(stream_kernel<1>, dim3((unsigned)nb), dim3(256), 0,
+                           s, a, b, c, sc, n);
+    return hipGetLastError();
+}
+
+// Zero the counter word of a partials buffer (a kernel, not a memset, so
+// that the call can sit in a captured graph).
+hipError_t launch_dot_reset(double *partials, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_kernel<double>, dim3(1), dim3(256), 0, s,
+                       partials + kRedBlocks, (int64_t)1, 0.0);
+    return hipGetLastError();
+}
+
 hipError_t launch_dot(const double *x, const double *y, int64_t n,
                       double *partials, double *out, hipStream_t s)
 {
@@ -825,11 +881,11 @@ hipError_t launch_update_p(const double *z, double *p, int64_t n,
 
 hipError_t launch_update_xr(double *x, double *r, const double *p,
                             const double *ap, int64_t n, double *sc,
-                            double *partials, hipStream_t s)
+                            double *partials, int iter, hipStream_t s)
 {
     hipLaunchKernelGGL(update_xr_kernel, dim3(blocks_for(n, 256, kRedBlocks)),
                        dim3(256), 0, s, x, r, p, ap, n, sc, partials,
-                       counter_of(partials));
+                       counter_of(partials), iter);
     return hipGetLastError();
 }
 

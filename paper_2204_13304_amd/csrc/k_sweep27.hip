@@ -505,7 +505,7 @@ static hipError_t c27_launch_dir(const C27Args<T> &a, bool bwd, bool zero,
 }
 
 template <int MODE, bool BWD>
-static hipError_t c27_launch_ilu(const C27Args<double> &a, int nw, int grid,
+static hipError_t c27_launch_dilu(const C27Args<double> &a, int nw, int grid,
                                  size_t lds, hipStream_t s)
 {
     // 4 compute wavefronts would need more LDS than a CU has with the
@@ -517,7 +517,7 @@ static hipError_t c27_launch_ilu(const C27Args<double> &a, int nw, int grid,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_ilu27(const m2s_stencil &A, int mode, const void *r,
+hipError_t launch_dilu27(const m2s_stencil &A, int mode, const void *r,
                         const void *w, void *out, Workspace &ws,
                         const SweepPlan &plan, hipStream_t s)
 {
@@ -551,13 +551,13 @@ hipError_t launch_ilu27(const m2s_stencil &A, int mode, const void *r,
     case 1:  // factor: w = 1 / (diag - off^2 S), forward
         a.off = A.offdiag * A.offdiag;
         a.diagc = A.diag;
-        return c27_launch_ilu<1, false>(a, nw, plan.grid, lds, s);
+        return c27_launch_dilu<1, false>(a, nw, plan.grid, lds, s);
     case 2:  // lower solve, forward
         a.off = A.offdiag;
-        return c27_launch_ilu<2, false>(a, nw, plan.grid, lds, s);
+        return c27_launch_dilu<2, false>(a, nw, plan.grid, lds, s);
     case 3:  // upper solve, backward
         a.off = A.offdiag;
-        return c27_launch_ilu<3, true>(a, nw, plan.grid, lds, s);
+        return c27_launch_dilu<3, true>(a, nw, plan.grid, lds, s);
     }
     return hipErrorInvalidValue;
 }

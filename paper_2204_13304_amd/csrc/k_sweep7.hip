@@ -564,12 +564,19 @@ hipError_t launch_sweep7(const m2s_stencil &A, const Block7Consts &C,
     }
     if (!ws.b7c_valid ||
         std::memcmp(&ws.b7c_host, &C, sizeof(Block7Consts)) != 0) {
-        hipError_t e = hipStreamSynchronize(s);
-        if (e == hipSuccess)
-            e = hipMemcpy(ws.b7c, &C, sizeof(Block7Consts),
-                          hipMemcpyHostToDevice);
-        if (e != hipSuccess) return e;
+        // ordered on the sweep's stream: after the sweeps already queued
+        // there (which may still read the old constants), before this one;
+        // the wait for the copy keeps the host source valid until it is
+        // read (the constants change only with the blocks or omega)
         std::memcpy(&ws.b7c_host, &C, sizeof(Block7Consts));
+        hipError_t e = hipMemcpyAsync(ws.b7c, &ws.b7c_host,
+                                      sizeof(Block7Consts),
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            ws.b7c_valid = false;
+            return e;
+        }
         ws.b7c_valid = true;
     }
     const size_t lds = b7_lds_bytes(1);

@@ -284,10 +284,17 @@ size_t c27_lds_bytes(int nw, m2s_dtype t, int mode);
 // ILU of the 27-point operator on the same tiles (F64): mode 1 factor
 // (out = w = 1/d), 2 lower solve (out = y from r), 3 upper solve (out = z
 // from r = y); w is the factor's weight array for modes 2 and 3.
-hipError_t launch_ilu27(const m2s_stencil &A, int mode, const void *r,
+hipError_t launch_dilu27(const m2s_stencil &A, int mode, const void *r,
                         const void *w, void *out, Workspace &ws,
                         const SweepPlan &plan, hipStream_t s);
 int c27_threads(int nw);  // nw compute + nw memory + 1 poll wavefronts
+// ILU(0) of the 27-point operator, hyperplane by hyperplane (k_ilu0.hip):
+// L (13 per point), U (14 per point), z = (L U)^{-1} r.
+hipError_t launch_ilu0_factor(const m2s_stencil &A, double *L, double *U,
+                              hipStream_t s);
+hipError_t launch_ilu0_apply(const m2s_stencil &A, const double *L,
+                             const double *U, const double *r, double *z,
+                             hipStream_t s);
 // Tiling of the block SSOR sweep: rectangular tiles of 16 j by 4 * nw k.
 struct B7Layout {
     int nw, kt, njt, nbands, ntiles, ns, wb;
@@ -331,13 +338,18 @@ inline size_t c27_record_bytes(m2s_dtype t) { return t == M2S_F64 ? 16 : 8; }
 
 // CG vector kernels (double).  Scalars live in a small device array `sc`.
 // SC_BD latches a breakdown (p.Ap <= 0 or a non-finite r.z, p.Ap) on the
-// device, so that a solve need not read the scalars back every iteration.
+// device, so that a solve need not read the scalars back every iteration;
+// SC_BDIT holds the iteration that latched it.  From that iteration on the
+// update kernels leave x, r and p as they are.
 enum CgScalar {
-    SC_RZ = 0, SC_RZ_OLD, SC_PAP, SC_RR, SC_BD, SC_N
+    SC_RZ = 0, SC_RZ_OLD, SC_PAP, SC_RR, SC_BD, SC_BDIT, SC_N
 };
 int dot_partials_capacity();
 hipError_t launch_dot(const double *x, const double *y, int64_t n,
                       double *partials, double *out, hipStream_t s);
+hipError_t launch_dot_reset(double *partials, hipStream_t s);
+hipError_t launch_stream(int kind, const double *a, const double *b,
+                         double *c, double sc, int64_t n, hipStream_t s);
 // r = b - Ax (Ax given) and rr = r.r
 hipError_t launch_residual(const double *b, const double *ax, double *r,
                            int64_t n, double *partials, double *rr_out,
@@ -348,7 +360,7 @@ hipError_t launch_update_p(const double *z, double *p, int64_t n,
 // x += alpha p ; r -= alpha Ap ; rr = r.r ; alpha = rz / pAp
 hipError_t launch_update_xr(double *x, double *r, const double *p,
                             const double *ap, int64_t n, double *sc,
-                            double *partials, hipStream_t s);
+                            double *partials, int iter, hipStream_t s);
 // Ap = A p and pAp = p.Ap fused (CONST27/VAR7 double)
 hipError_t launch_spmv_dot(const m2s_stencil &A, const double *p, double *ap,
                            double *partials, double *out, hipStream_t s);

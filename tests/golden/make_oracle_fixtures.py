@@ -37,6 +37,8 @@ if ROOT not in sys.path:
 import oracle  # noqa: E402
 from paper_2204_13304_amd import inputs  # noqa: E402
 
+# the oracle's solver core (the microbenchmark routines live in
+# oracle/m2s_oracle_micro.h and do not take part in these runs)
 ORACLE_SOURCES = ("oracle/m2s_oracle.c", "oracle/m2s_oracle_impl.h")
 C3_FILE = os.path.join(HERE, "oracle_c3_mgpcg_256.json")
 C5_FILE = os.path.join(HERE, "oracle_c5_var7_128.json")

@@ -26,3 +26,25 @@ def rel_inf(a, ref):
 
 def banner(msg):
     print(f"[gpu-test] {msg}", flush=True)
+
+
+def oracle_fixture(name):
+    """A stored oracle result (tests/golden/, written by
+    tests/golden/make_oracle_fixtures.py from the CPU oracle only)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def strided(a, stride):
+    """Flat C-order entries 0, stride, 2 stride, ... (the fixtures'
+    samples)."""
+    return np.ascontiguousarray(a).ravel()[::stride]
+
+
+def rel_sample(a, ref):
+    """max |a - ref| / max |ref| over a sample."""
+    a, ref = np.asarray(a, np.float64), np.asarray(ref, np.float64)
+    return float(np.max(np.abs(a - ref)) / np.max(np.abs(ref)))

@@ -17,7 +17,7 @@ def test_library_exports_every_header_symbol():
 
 def test_status_strings_and_version():
     lib = L.load()
-    assert lib.m2s_version() >= 10000
+    assert lib.m2s_version() >= 20000
     for s in range(10):
         assert lib.m2s_status_string(s)
 
@@ -163,3 +163,28 @@ def test_bench_refuses_more_than_one_gpu():
     assert out.returncode == 2
     msg = json.loads(out.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"]
+
+
+def test_pcg_workspace_argument_errors():
+    """m2s_pcg_workspace_create and m2s_pcg_solve_ws validate on the host
+    before anything is allocated or launched (no GPU needed)."""
+    lib = L.load()
+    s = L.StencilC()
+    s.kind, s.dtype = L.CONST27, L.F64
+    s.ext = L.Extent(8, 8, 8)
+    s.diag, s.offdiag = 26.0, -1.0
+    h = C.c_void_p()
+    assert lib.m2s_pcg_workspace_create(C.byref(s), None) == 1      # ARG
+    assert lib.m2s_pcg_workspace_create(None, C.byref(h)) == 1
+    s.dtype = L.F32
+    assert lib.m2s_pcg_workspace_create(C.byref(s), C.byref(h)) == 3  # DTYPE
+    s.dtype = L.F64
+    opts = L.PcgOpts(1, 0.0, 0)
+    info = L.PcgInfo()
+    P = C.c_void_p
+    b, x = P(1 << 40), P((1 << 40) + 8 * 512)
+    # no workspace
+    assert lib.m2s_pcg_solve_ws(C.byref(s), L.PC_NONE, None, b, x,
+                                C.byref(opts), C.byref(info), None, None,
+                                None) == 1
+    lib.m2s_pcg_workspace_destroy(None)   # a null workspace is ignored

@@ -110,6 +110,23 @@ def test_full_size_ssor_162(m):
     assert rel_inf(host(xg), ref) <= 1e-13
 
 
+def test_full_size_ssor_162_random_start(m):
+    # two SSOR iterations at 162^3 x 5 from a random x0, so that the forward
+    # half-sweep reads non-zero old values across every tile boundary
+    shape = (162, 162, 162)
+    banner("ssor 162^3 x 5, random x0, 2 iterations")
+    B = inputs.block7_blocks(4)
+    A = m.block7(shape, B)
+    b = oracle.spmv_block7(np.ones(shape + (5,)), B)
+    x0 = inputs.standard_normal(73, shape + (5,))
+    xg = dev(x0)
+    ref = x0
+    for _ in range(2):
+        m.ssor_sweep(A, dev(b), xg, 1.2, "sym")
+        ref = oracle.ssor_block7(b, ref, B, 1.2, "sym")
+    assert rel_inf(host(xg), ref) <= 1e-13
+
+
 def test_ssor_rejects_bad_omega(m):
     A = m.block7((4, 4, 4), inputs.block7_blocks(4))
     x = torch.zeros((4, 4, 4, 5), dtype=torch.float64, device="cuda")

@@ -10,7 +10,8 @@ import torch
 
 import oracle
 from paper_2204_13304_amd import inputs
-from tests.gpu_util import banner, dev, host, rel_inf
+from tests.gpu_util import (banner, dev, host, oracle_fixture, rel_inf,
+                             rel_sample, strided)
 
 pytestmark = pytest.mark.gpu
 
@@ -118,25 +119,46 @@ def test_pcg_mg_256_two_iterations(m):
 
 def test_pcg_256_to_tolerance_fp64_and_mixed(m):
     """The benchmark's time-to-solution runs at 256^3 (rtol 1e-9; mixed:
-    FP32 V-cycle, residual replaced every 50 iterations).  The oracle cannot
-    run them to convergence at this size in a test, so they are checked by
-    what holds at any size: both reach a true FP64 residual <= 1e-9 within
-    a couple of iterations of each other, and agree to the accuracy the
-    tolerance allows."""
+    FP32 V-cycle, residual replaced every 50 iterations) against the stored
+    oracle runs of the same configuration (oracle_c3_mgpcg_256.json):
+    iteration counts within one, residual histories while above 1e-10, and
+    a strided sample of x; the mixed solution also against the FP64
+    oracle's."""
     shape, b = _bench_problem_256()
-    banner("pcg mg 256^3 to 1e-9, fp64 and mixed")
+    fx = oracle_fixture("oracle_c3_mgpcg_256.json")
+    stride = fx["sample_stride"]
+    banner("pcg mg 256^3 to 1e-9, fp64 and mixed, against the oracle")
     A = m.const27(shape)
     bd = dev(b)
-    out = {}
+    xs = {}
     for tag, prec, rep in (("fp64", torch.float64, 0),
                            ("mixed", torch.float32, 50)):
+        ref = fx[tag]
+        assert ref["replace_every"] == rep
         mg = m.MG(A, 4, prec=prec)
         x, info = m.pcg_solve(A, bd, None, "mg", mg, max_iter=400, rtol=1e-9,
-                              replace_every=rep)
+                              replace_every=rep, history=True)
         assert info["true_rel_res"] <= 1e-9, tag
-        out[tag] = (host(x), info["iters"])
-    assert abs(out["fp64"][1] - out["mixed"][1]) <= 2
-    assert rel_inf(out["mixed"][0], out["fp64"][0]) <= 1e-7
+        assert abs(info["iters"] - ref["iters"]) <= 1, (tag, info["iters"],
+                                                        ref["iters"])
+        h, hr = np.asarray(info["hist"]), np.asarray(ref["hist"])
+        k = min(len(h), len(hr))
+        k = int(np.argmax(hr[:k] < 1e-10)) if np.any(hr[:k] < 1e-10) else k
+        herr = float(np.max(np.abs(h[:k] - hr[:k]) / hr[:k]))
+        xs[tag] = strided(host(x), stride)
+        xerr = rel_sample(xs[tag], ref["x_sample"])
+        print(f"[c3 {tag}] iters {info['iters']} (oracle {ref['iters']}), "
+              f"history rel err {herr:.2e}, x sample rel err {xerr:.2e}",
+              flush=True)
+        # FP64: the two runs differ only in summation order (measured
+        # 5.5e-9).  Mixed: the float V-cycle's output differs from the float
+        # oracle's at float rounding (~1e-7 relative, test_vcycle_f32) in
+        # every iteration, so the histories agree to float level only
+        # (measured 4.7e-6); the solutions still agree to 2.3e-11.
+        assert herr <= (1e-6 if tag == "fp64" else 1e-4), (tag, herr)
+        assert xerr <= (1e-10 if tag == "fp64" else 1e-9), (tag, xerr)
+    # the mixed solution against the FP64 oracle's
+    assert rel_sample(xs["mixed"], fx["fp64"]["x_sample"]) <= 1e-7
 
 
 def test_pcg_mixed_precision(m):
@@ -151,7 +173,7 @@ def test_pcg_mixed_precision(m):
                      replace_every=50)
     r64 = oracle.pcg(b, precond="mg", levels=4, max_iter=200, tol=1e-9)
     assert i32["true_rel_res"] <= 1e-9
-    assert abs(i32["iters"] - r32["iters"]) <= 2
+    assert abs(i32["iters"] - r32["iters"]) <= 1
     assert rel_inf(host(x32), r64["x"]) <= 1e-7
 
 
@@ -204,13 +226,50 @@ def test_pcg_warm_start_resumes(m):
 def test_pcg_breakdown_latched_in_fixed_iteration_run(m):
     # rtol <= 0 without history: the scalars are read back only after the
     # last iteration, so the breakdown is latched on the device and
-    # reported then
+    # reported then -- with the same x and iteration as the run that reads
+    # the scalars back every iteration (the update kernels stop at the
+    # breakdown)
     shape = (8, 8, 8)
     A = m.const27(shape, diag=-26.0)
     b = dev(np.ones(shape))
-    _, info = m.pcg_solve(A, b, None, "none", max_iter=10, rtol=0.0,
-                          raise_on_error=False)
-    assert info["status"] == "M2S_ERR_BREAKDOWN" and info["iters"] == 10
+    x0 = dev(inputs.standard_normal(3, shape))
+    xl, info = m.pcg_solve(A, b, x0.clone(), "none", max_iter=10, rtol=0.0,
+                           raise_on_error=False)
+    xe, eager = m.pcg_solve(A, b, x0.clone(), "none", max_iter=10,
+                            rtol=1e-30, raise_on_error=False)
+    assert info["status"] == "M2S_ERR_BREAKDOWN"
+    assert eager["status"] == "M2S_ERR_BREAKDOWN"
+    assert info["iters"] == eager["iters"] >= 1
+    assert torch.equal(xl, xe)
+    # the operator is negative definite: p.Ap < 0 in the first iteration,
+    # so x is left at x0
+    assert info["iters"] == 1 and torch.equal(xl, x0)
+
+
+def test_pcg_workspace_reuse(m):
+    # a solve with a reusable workspace (m2s_pcg_solve_ws) gives the bits of
+    # the allocating entry point, call after call; another extent is
+    # refused
+    shape = (24, 20, 16)
+    A = m.const27(shape)
+    b = dev(oracle.spmv27(np.ones(shape)) +
+            inputs.rhs_perturbation(4, shape))
+    mg = m.MG(A, 3)
+    ref, ri = m.pcg_solve(A, b, None, "mg", mg, max_iter=40, rtol=1e-10)
+    ws = m.PcgWorkspace(A)
+    for _ in range(2):
+        for pc in ("mg", "symgs", "none"):
+            x1, i1 = m.pcg_solve(A, b, None, pc, mg, max_iter=25, rtol=0.0,
+                                 ws=ws)
+            x2, i2 = m.pcg_solve(A, b, None, pc, mg, max_iter=25, rtol=0.0)
+            assert torch.equal(x1, x2) and i1["iters"] == i2["iters"] == 25
+    xm, im = m.pcg_solve(A, b, None, "mg", mg, max_iter=40, rtol=1e-10,
+                         ws=ws)
+    assert torch.equal(xm, ref) and im["iters"] == ri["iters"]
+    B = m.const27((16, 16, 16))
+    with pytest.raises(RuntimeError, match="M2S_ERR_SHAPE"):
+        m.pcg_solve(B, dev(np.ones((16, 16, 16))), None, "none",
+                    max_iter=2, ws=ws)
 
 
 def test_pcg_breakdown_reported(m):

@@ -161,38 +161,38 @@ def test_bt_lines_rejects_bad_arguments(m):
 @pytest.mark.parametrize("shape", [(9, 7, 6), (16, 16, 16), (13, 26, 9),
                                    (33, 20, 17), (1, 1, 5)])
 @pytest.mark.parametrize("nw", ["1", "2"])
-def test_ilu27_factor_and_apply(m, shape, nw, monkeypatch):
-    banner(f"ilu27 {shape} nw {nw}")
+def test_dilu27_factor_and_apply(m, shape, nw, monkeypatch):
+    banner(f"dilu27 {shape} nw {nw}")
     monkeypatch.setenv("M2S_C27_WAVES", nw)
     A = m.const27(shape)
     ws = m.Workspace(A)
-    w = m.ilu27_factor(A, ws)
-    d = oracle.ilu27_factor(shape)
+    w = m.dilu27_factor(A, ws)
+    d = oracle.dilu27_factor(shape)
     assert rel_inf(host(w), 1.0 / d) <= 1e-13
     r = inputs.standard_normal(50, shape)
-    z = m.ilu27_apply(A, w, dev(r), ws=ws)
-    assert rel_inf(host(z), oracle.ilu27_solve(d, r)) <= 1e-13
+    z = m.dilu27_apply(A, w, dev(r), ws=ws)
+    assert rel_inf(host(z), oracle.dilu27_solve(d, r)) <= 1e-13
 
 
-def test_ilu27_full_size_256(m):
+def test_dilu27_full_size_256(m):
     shape = (256, 256, 256)
-    banner("ilu27 256^3")
+    banner("dilu27 256^3")
     A = m.const27(shape)
     ws = m.Workspace(A)
-    w = m.ilu27_factor(A, ws)
-    d = oracle.ilu27_factor(shape)
+    w = m.dilu27_factor(A, ws)
+    d = oracle.dilu27_factor(shape)
     assert rel_inf(host(w), 1.0 / d) <= 1e-13
     r = inputs.standard_normal(51, shape)
-    z = m.ilu27_apply(A, w, dev(r), ws=ws)
-    assert rel_inf(host(z), oracle.ilu27_solve(d, r)) <= 1e-13
+    z = m.dilu27_apply(A, w, dev(r), ws=ws)
+    assert rel_inf(host(z), oracle.dilu27_solve(d, r)) <= 1e-13
 
 
-def test_ilu27_rejects_tall_tiles_and_f32(m, monkeypatch):
+def test_dilu27_rejects_tall_tiles_and_f32(m, monkeypatch):
     monkeypatch.setenv("M2S_C27_WAVES", "4")
     A = m.const27((8, 8, 8))
     ws = m.Workspace(A)
     with pytest.raises(RuntimeError):
-        m.ilu27_factor(A, ws)
+        m.dilu27_factor(A, ws)
     # a rejected call leaves the workspace usable
     rh = inputs.standard_normal(53, (8, 8, 8))
     x = dev(np.zeros((8, 8, 8)))
@@ -202,4 +202,44 @@ def test_ilu27_rejects_tall_tiles_and_f32(m, monkeypatch):
     monkeypatch.setenv("M2S_C27_WAVES", "2")
     A32 = m.const27((8, 8, 8), dtype=torch.float32)
     with pytest.raises(RuntimeError):
-        m.ilu27_factor(A32)
+        m.dilu27_factor(A32)
+
+
+@pytest.mark.parametrize("shape", [(9, 7, 6), (16, 16, 16), (13, 26, 9),
+                                   (1, 1, 5), (2, 2, 2), (5, 1, 7)])
+def test_ilu0_factor_and_apply(m, shape):
+    # ILU(0) (Sec. 7.2.1 / Sec. 9): the factor against the oracle's, entry by
+    # entry, and the solve z = (L U)^{-1} r
+    banner(f"ilu0 {shape}")
+    A = m.const27(shape)
+    Lg, Ug = m.ilu0_factor(A)
+    Lo, Uo = oracle.ilu0_27_factor(shape)
+    assert rel_inf(host(Lg), Lo) <= 1e-13
+    assert rel_inf(host(Ug), Uo) <= 1e-13
+    r = inputs.standard_normal(54, shape)
+    z = m.ilu0_apply(A, Lg, Ug, dev(r))
+    assert rel_inf(host(z), oracle.ilu0_27_solve(Lo, Uo, r)) <= 1e-13
+
+
+def test_ilu0_full_size_256(m):
+    shape = (256, 256, 256)
+    banner("ilu0 256^3")
+    A = m.const27(shape)
+    Lg, Ug = m.ilu0_factor(A)
+    Lo, Uo = oracle.ilu0_27_factor(shape)
+    assert rel_inf(host(Lg), Lo) <= 1e-13
+    assert rel_inf(host(Ug), Uo) <= 1e-13
+    r = inputs.standard_normal(55, shape)
+    z = m.ilu0_apply(A, Lg, Ug, dev(r))
+    assert rel_inf(host(z), oracle.ilu0_27_solve(Lo, Uo, r)) <= 1e-13
+
+
+def test_ilu0_rejects_other_kinds_and_aliasing(m):
+    A32 = m.const27((4, 4, 4), dtype=torch.float32)
+    with pytest.raises((RuntimeError, TypeError)):
+        m.ilu0_factor(A32)
+    A = m.const27((4, 4, 4))
+    Lg, Ug = m.ilu0_factor(A)
+    r = dev(np.ones((4, 4, 4)))
+    with pytest.raises(RuntimeError, match="M2S_ERR_ALIAS"):
+        m.ilu0_apply(A, Lg, Ug, r, r)

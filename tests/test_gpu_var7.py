@@ -10,7 +10,8 @@ import torch
 
 import oracle
 from paper_2204_13304_amd import inputs
-from tests.gpu_util import banner, dev, host, rel_inf
+from tests.gpu_util import (banner, dev, host, oracle_fixture, rel_inf,
+                             rel_sample, strided)
 
 pytestmark = pytest.mark.gpu
 
@@ -325,3 +326,49 @@ def test_tile_wait_timeout_is_reported_and_recovered(m, monkeypatch):
     ws.check()
     ref = oracle.symgs_var7(r, x0, pr["kx"], pr["ky"], pr["kz"], "sym")
     assert rel_inf(host(xg), ref) <= 1e-13
+
+
+def test_solve_128_against_oracle(m):
+    """The differentiable solve's configuration at full size (128^3, seed 5,
+    4 levels, rtol 1e-10) against the stored oracle run
+    (oracle_c5_var7_128.json): forward and adjoint MG-PCG iteration counts
+    within one, strided samples of u, lam = dL/df and dL/dk from the
+    face-gradient kernel, and the first 20 residuals.  With these
+    log-normal faces (contrast about e^4) the CG residual norms of two runs
+    that differ only in summation order agree to 1e-13 for about 30
+    iterations, then drift apart to a few per cent at the same iteration
+    count (measured: up to 14 % in the late history) while the solutions
+    still agree to 2e-10 -- so the later history is compared through the
+    iteration count and the solutions."""
+    shape = (128, 128, 128)
+    fx = oracle_fixture("oracle_c5_var7_128.json")
+    stride = fx["sample_stride"]
+    banner("var7 128^3 solve, adjoint and gradient against the oracle")
+    pr = inputs.var7_problem(5, shape)
+    A = _A(m, pr)
+    mg = m.MG(A, 4)
+    out = {}
+    for tag, rhs in (("forward", dev(pr["f"])), ("adjoint", None)):
+        if tag == "adjoint":
+            rhs = out["forward"] - dev(pr["u_t"])
+        x, info = m.pcg_solve(A, rhs, None, "mg", mg, max_iter=500,
+                              rtol=1e-10, history=True)
+        ref = fx[tag]
+        assert info["true_rel_res"] <= 1e-10, tag
+        assert abs(info["iters"] - ref["iters"]) <= 1, (tag, info["iters"],
+                                                        ref["iters"])
+        h, hr = np.asarray(info["hist"][:21]), np.asarray(ref["hist"][:21])
+        herr = float(np.max(np.abs(h - hr) / hr))
+        print(f"[c5 {tag}] iters {info['iters']} (oracle {ref['iters']}), "
+              f"first 20 residuals rel err {herr:.2e}", flush=True)
+        assert herr <= 1e-9, (tag, herr)
+        out[tag] = x
+    u, lam = out["forward"], out["adjoint"]
+    g = m.face_grad(A, u, lam)
+    errs = {}
+    for name, got in (("u_sample", u), ("lam_sample", lam), ("gkx_sample", g[0]),
+                      ("gky_sample", g[1]), ("gkz_sample", g[2])):
+        errs[name] = rel_sample(strided(host(got), stride), fx[name])
+    print(f"[c5] sample rel errs {errs}", flush=True)
+    for name, e in errs.items():
+        assert e <= 1e-8, (name, e)

@@ -1,5 +1,6 @@
 """Pins of the oracle's microbenchmark routines (Sec. 7.2.1: Jacobi
-iterations of a 2-D 9-point stencil, the 27-point ILU) and of its
+iterations of a 2-D 9-point stencil, the 27-point ILU(0) and the
+factored-diagonal D-ILU) and of its
 pentadiagonal and 5x5 block-tridiagonal line solves (the SP- and
 BT-shaped systems of Sec. 7.1), against
 closed forms, fixed points, defining properties and library routines
@@ -70,10 +71,10 @@ def test_jacobi9_converges_to_solution():
 
 # ---------------------------------------------------------------- ILU
 @pytest.mark.parametrize("shape", [(3, 4, 5), (2, 6, 3), (4, 4, 4)])
-def test_ilu27_diagonal_of_factor_matches_operator(shape):
+def test_dilu27_diagonal_of_factor_matches_operator(shape):
     nz, ny, nx = shape
     A = _A27(nz, ny, nx)
-    d = oracle.ilu27_factor(shape).ravel()
+    d = oracle.dilu27_factor(shape).ravel()
     L, U, D = sp.tril(A, -1), sp.triu(A, 1), sp.diags(d)
     M = ((D + L) @ sp.diags(1.0 / d) @ (D + U)).toarray()
     assert np.max(np.abs(np.diag(M) - 26.0)) <= 1e-13
@@ -86,31 +87,121 @@ def test_ilu27_diagonal_of_factor_matches_operator(shape):
 
 
 @pytest.mark.parametrize("shape", [(3, 4, 5), (5, 3, 2)])
-def test_ilu27_solve_inverts_factor(shape):
+def test_dilu27_solve_inverts_factor(shape):
     nz, ny, nx = shape
     A = _A27(nz, ny, nx)
-    d = oracle.ilu27_factor(shape)
+    d = oracle.dilu27_factor(shape)
     r = np.random.default_rng(2).standard_normal(shape)
-    z = oracle.ilu27_solve(d, r).ravel()
+    z = oracle.dilu27_solve(d, r).ravel()
     dv = d.ravel()
     L, U, D = sp.tril(A, -1), sp.triu(A, 1), sp.diags(dv)
     Mz = (D + L) @ ((D + U) @ z / dv)
     assert np.max(np.abs(Mz - r.ravel())) <= 1e-13
 
 
-def test_ilu27_is_exact_on_a_line():
+def test_dilu27_is_exact_on_a_line():
     # one grid line: the 27-point operator is tridiagonal and its ILU the
     # exact LU factorisation
     shape = (1, 1, 23)
     A = _A27(*shape)
-    d = oracle.ilu27_factor(shape)
+    d = oracle.dilu27_factor(shape)
     r = np.random.default_rng(3).standard_normal(shape)
-    z = oracle.ilu27_solve(d, r).ravel()
+    z = oracle.dilu27_solve(d, r).ravel()
     ref = spla.spsolve(A.tocsc(), r.ravel())
     assert np.max(np.abs(z - ref)) <= 1e-14 * np.abs(ref).max()
 
 
 # -------------------------------------------------- pentadiagonal lines
+def _ilu0_matrices(Lf, Uf):
+    """Assemble the unit lower L and the upper U from the ILU(0) factor
+    arrays (offsets in lexicographic (dk, dj, di) order)."""
+    nz, ny, nx = Lf.shape[:3]
+    n = nx * ny * nz
+    L = np.eye(n)
+    U = np.zeros((n, n))
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                p = (k * ny + j) * nx + i
+                U[p, p] = Uf[k, j, i, 0]
+                for m in range(27):
+                    dk, dj, di = m // 9 - 1, (m // 3) % 3 - 1, m % 3 - 1
+                    kk, jj, ii = k + dk, j + dj, i + di
+                    if not (0 <= kk < nz and 0 <= jj < ny and 0 <= ii < nx):
+                        continue
+                    q = (kk * ny + jj) * nx + ii
+                    if m < 13:
+                        L[p, q] = Lf[k, j, i, m]
+                    elif m > 13:
+                        U[p, q] = Uf[k, j, i, 1 + m - 14]
+    return L, U
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 5), (2, 6, 3), (4, 4, 4),
+                                   (5, 5, 5), (1, 4, 7)])
+def test_ilu0_27_reproduces_operator_on_its_pattern(shape):
+    # the defining property of ILU(0): L unit lower and U upper with the
+    # pattern of A, and (L U)_pq = a_pq on that pattern (the fill outside it
+    # dropped)
+    nz, ny, nx = shape
+    A = _A27(nz, ny, nx).toarray()
+    Lf, Uf = oracle.ilu0_27_factor(shape)
+    L, U = _ilu0_matrices(Lf, Uf)
+    pat = A != 0
+    assert np.all(np.tril(L, -1)[~pat] == 0) and np.all(np.triu(U, 1)[~pat] == 0)
+    LU = L @ U
+    assert np.max(np.abs(LU[pat] - A[pat])) <= 1e-13
+    # fill outside the pattern exists (it is not the complete LU)
+    if min(shape) >= 3:
+        assert np.max(np.abs(LU[~pat])) > 1e-3
+
+
+def test_ilu0_27_differs_from_the_factored_diagonal_variant():
+    # the factored-diagonal variant (D-ILU) keeps A's off-diagonals, so its
+    # M = (D + L) D^{-1} (D + U) misses the off-diagonal pattern entries that
+    # ILU(0) reproduces
+    shape = (4, 4, 4)
+    A = _A27(*shape)
+    d = oracle.dilu27_factor(shape).ravel()
+    L, U, D = sp.tril(A, -1), sp.triu(A, 1), sp.diags(d)
+    M = ((D + L) @ sp.diags(1.0 / d) @ (D + U)).toarray()
+    pat = A.toarray() != 0
+    assert np.max(np.abs(M[pat] - A.toarray()[pat])) > 1e-3
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 5), (4, 4, 4)])
+def test_ilu0_27_factors_are_symmetric(shape):
+    # A is symmetric, so L = U^T diag(U)^{-1}: l_pq = u_qp / u_qq (the form
+    # the GPU factor stores, 14 values per point)
+    Lf, Uf = oracle.ilu0_27_factor(shape)
+    L, U = _ilu0_matrices(Lf, Uf)
+    Ls = np.tril(U.T / np.diag(U)[None, :], -1) + np.eye(L.shape[0])
+    assert np.max(np.abs(L - Ls)) <= 1e-14
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 5), (5, 3, 2), (6, 6, 6)])
+def test_ilu0_27_solve_inverts_LU(shape):
+    Lf, Uf = oracle.ilu0_27_factor(shape)
+    L, U = _ilu0_matrices(Lf, Uf)
+    r = np.random.default_rng(7).standard_normal(shape)
+    z = oracle.ilu0_27_solve(Lf, Uf, r).ravel()
+    res = L @ (U @ z) - r.ravel()
+    assert np.max(np.abs(res)) <= 1e-13 * np.abs(r).max()
+
+
+@pytest.mark.parametrize("shape", [(2, 2, 2), (1, 1, 17), (1, 2, 2)])
+def test_ilu0_27_is_exact_when_nothing_is_dropped(shape):
+    # on a 2x2x2 grid every point neighbours every other (A is dense), and
+    # on one line A is tridiagonal: no fill-in is dropped, so ILU(0) is the
+    # complete LU and the solve is A^{-1} r
+    A = _A27(*shape).toarray()
+    Lf, Uf = oracle.ilu0_27_factor(shape)
+    r = np.random.default_rng(8).standard_normal(shape)
+    z = oracle.ilu0_27_solve(Lf, Uf, r).ravel()
+    ref = scipy.linalg.solve(A, r.ravel())
+    assert np.max(np.abs(z - ref)) <= 1e-14 * np.abs(ref).max() * 10
+
+
 def _penta(shape, seed):
     rng = np.random.default_rng(seed)
     coef = rng.uniform(-1.0, 1.0, (5,) + shape)
