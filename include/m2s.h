@@ -335,6 +335,23 @@ m2s_status m2s_convert(const void *src, m2s_dtype src_t, void *dst,
                        m2s_dtype dst_t, int64_t n, hipStream_t stream);
 
 /* ---------------------------------------------------------------------
+ * m2s_dot_noalloc: m2s_dot for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, same kernels and reduction order, so the
+ * same bits as m2s_dot; it calls no allocator.  Its reduction scratch (1024
+ * per-block partial sums and a counter: 1032 doubles, 8256 bytes) is a
+ * fixed device array of the library, one per GPU, held from the first call
+ * on that GPU until the process ends; the call clears the counter itself.
+ * Any n >= 0 fits (the partials do not grow with n); should the reduction
+ * ever need more partials than the array holds, the call returns
+ * M2S_ERR_UNSUPPORTED.  Every call on one GPU shares that array: calls
+ * that overlap on one GPU (concurrent streams, threads) race and must be
+ * ordered by the caller.  M2S_ERR_ARG for null pointers or n < 0.
+ * --------------------------------------------------------------------- */
+m2s_status m2s_dot_noalloc(const double *x, const double *y, int64_t n,
+                           double *out, hipStream_t stream);
+
+/* ---------------------------------------------------------------------
  * Reference streaming passes for measurement (not a step of the method):
  * kind 0 copies c = a, kind 1 is the STREAM triad c = a + s*b, over n
  * doubles (device, 16-byte aligned; c must not overlap a or b).  They give

@@ -100,6 +100,7 @@ _SIGS = {
     "m2s_ilu0_factor": (C.c_int, [_S, _P, _P, _P]),
     "m2s_ilu0_apply": (C.c_int, [_S, _P, _P, _P, _P, _P]),
     "m2s_dot": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
+    "m2s_dot_noalloc": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
     "m2s_convert": (C.c_int, [_P, C.c_int, _P, C.c_int, C.c_int64, _P]),
     "m2s_stream": (C.c_int, [C.c_int32, _P, _P, _P, C.c_double, C.c_int64,
                              _P]),

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -840,7 +841,55 @@ m2s_status m2s_dot(const double *x, const double *y, int64_t n, double *out,
 
 }  // extern "C"
 
+// Reduction scratch of m2s_dot_noalloc: the per-block partial sums and the
+// counter that launch_dot uses, as a file-scope device array (each GPU the
+// library runs on holds its own copy from module load until the process
+// ends).  Host code never passes the array's name to a kernel (on the host
+// it is only a stand-in): the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr int kDotScratchDoubles = 1032;
+static __device__ __align__(256) double scratch[kDotScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+m2s_status dot_scratch(double **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return M2S_ERR_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return M2S_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess ||
+            !p)
+            return M2S_ERR_HIP;
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return M2S_OK;
+}
+}  // namespace
+
 extern "C" {
+
+m2s_status m2s_dot_noalloc(const double *x, const double *y, int64_t n,
+                           double *out, hipStream_t stream)
+{
+    if (!x || !y || !out || n < 0) return M2S_ERR_ARG;
+    // the partials of launch_dot must fit the fixed scratch
+    if (dot_partials_capacity() > kDotScratchDoubles)
+        return M2S_ERR_UNSUPPORTED;
+    double *sp = nullptr;
+    m2s_status st = dot_scratch(&sp);
+    if (st != M2S_OK) return st;
+    // the scratch keeps the last call's contents: the counter starts at 0
+    hipError_t e = launch_dot_reset(sp, stream);
+    if (e == hipSuccess) e = launch_dot(x, y, n, sp, out, stream);
+    return e == hipSuccess ? M2S_OK : M2S_ERR_HIP;
+}
 
 m2s_status m2s_stream(int32_t kind, const double *a, const double *b,
                       double *c, double s, int64_t n, hipStream_t stream)
