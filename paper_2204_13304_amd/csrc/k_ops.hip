@@ -8,59 +8,6 @@
 
 namespace m2s {
 
-// --------------------------------------------------------------------------
-// CONST27 SpMV: a 64x4 (x,y) tile per workgroup marches along z over a
-// chunk of planes.  Each plane (tile + 1-point halo) is staged in LDS with
-// coalesced loads; a thread keeps the 3x3 plane sums of the planes below,
-// at and above its point in registers, so every x value is read from HBM
-// once per chunk and 9 times from LDS.
-//   y = diag * x + off * ((S9(k-1) + S8(k)) + S9(k+1))
-// S9 = 3x3 sum in a plane, S8 = the same without the centre.
-// --------------------------------------------------------------------------
-constexpr int SP_TX = 64, SP_TY = 4, SP_KCHUNK = 16;
-
-template <typename T>
-__device__ __forceinline__ void sp27_stage(T (*tile)[SP_TX + 2], const T *x,
-                                           const Grid &g, int i0, int j0,
-                                           int k)
-{
-    const int tid = threadIdx.y * SP_TX + threadIdx.x;
-    constexpr int W = SP_TX + 2, H = SP_TY + 2;
-    for (int e = tid; e < W * H; e += SP_TX * SP_TY) {
-        const int ty = e / W, tx = e - (e / W) * W;
-        const int i = i0 + tx - 1, j = j0 + ty - 1;
-        T v = T(0);
-        if (k >= 0 && k < g.nz && i >= 0 && i < g.nx && j >= 0 && j < g.ny)
-            v = x[g.idx(i, j, k)];
-        tile[ty][tx] = v;
-    }
-}
-
-template <typename T, bool DOT>
-__global__ void __launch_bounds__(SP_TX *SP_TY)
-    spmv27_kernel(Grid g, T diag, T off, const T *__restrict__ x,
-                  T *__restrict__ y, double *partials, double *dot_out,
-                  unsigned *counter);
-
-template <typename T>
-struct Plane9 {
-    T s9, s8, c;
-};
-
-template <typename T>
-__device__ __forceinline__ Plane9<T> sp27_sums(T (*tile)[SP_TX + 2])
-{
-    const int tx = threadIdx.x + 1, ty = threadIdx.y + 1;
-    T a = (tile[ty - 1][tx - 1] + tile[ty - 1][tx]) + tile[ty - 1][tx + 1];
-    T b = tile[ty][tx - 1] + tile[ty][tx + 1];
-    T c = (tile[ty + 1][tx - 1] + tile[ty + 1][tx]) + tile[ty + 1][tx + 1];
-    Plane9<T> p;
-    p.c = tile[ty][tx];
-    p.s8 = (a + b) + c;
-    p.s9 = (a + (b + p.c)) + c;
-    return p;
-}
-
 // Deterministic block reduction of one double per thread into partials[b];
 // the last block to finish sums the partials in index order into *out and
 // re-arms the counter.
@@ -106,39 +53,167 @@ __device__ void block_reduce_finish(double v, double *partials, double *out,
     }
 }
 
+// --------------------------------------------------------------------------
+// CONST27 SpMV.  A workgroup owns a 64 x 16 (x, y) tile of one layer of kc
+// planes and marches through the layer plane by plane.  Each plane of the
+// tile plus its 1-point halo is staged in LDS; its loads are issued two
+// planes ahead into registers, so two planes per workgroup are in flight
+// while the current one is summed.  A thread owns one x column of 4
+// consecutive rows (8 in FP32, whose tiles are 64 x 32: the same bytes per
+// staged plane) and keeps their 3x3 plane sums of the planes on either side
+// in registers; the 3x3 sums are built from row sums (3 LDS reads per row,
+// 6 rows for 4 points), so every x value is read from HBM once per layer,
+// and the halo rows and columns come from L2 when the tile that owns them
+// runs at the same time.
+//
+// Placement: workgroup w runs on XCD w mod 8, so the tiles (numbered layer
+// by layer, x fastest) are handed to the XCDs in contiguous blocks: the
+// tiles running together on one XCD are spatial neighbours and share their
+// halos in that XCD's L2.  About 512 workgroups (two per CU, 8 waves):
+// fewer leave too few loads in flight, more cut the layers thinner.
+//   y = diag * x + off * ((S9(k-1) + S8(k)) + S9(k+1))
+// S9 = 3x3 sum in a plane, S8 = the same without the centre.
+// --------------------------------------------------------------------------
+constexpr int SP_TX = 64, SP_W = SP_TX + 2;
+constexpr int SP_TARGET_WGS = 512;
+
+template <typename T>
+struct SpCfg {
+    static constexpr int TY = sizeof(T) == 8 ? 16 : 32;
+    static constexpr int R = TY / 4;  // rows per thread
+    static constexpr int H = TY + 2;
+    static constexpr int NQ = (SP_W * H + 255) / 256;  // staged values/thread
+};
+
+struct SpTiles {
+    int nbx, nby, kc, ntiles, per_xcd;
+};
+
+SpTiles sp_tiles(const Grid &g, int ty)
+{
+    SpTiles t;
+    t.nbx = (g.nx + SP_TX - 1) / SP_TX;
+    t.nby = (g.ny + ty - 1) / ty;
+    const int tpl = t.nbx * t.nby;
+    int layers = std::max(1, std::min(g.nz, (SP_TARGET_WGS + tpl - 1) / tpl));
+    t.kc = (g.nz + layers - 1) / layers;
+    layers = (g.nz + t.kc - 1) / t.kc;
+    t.ntiles = layers * tpl;
+    t.per_xcd = (t.ntiles + 7) / 8;
+    return t;
+}
+
 template <typename T, bool DOT>
-__global__ void __launch_bounds__(SP_TX *SP_TY)
-    spmv27_kernel(Grid g, T diag, T off, const T *__restrict__ x,
+__global__ void __launch_bounds__(256)
+    spmv27_kernel(Grid g, SpTiles t, T diag, T off, const T *__restrict__ x,
                   T *__restrict__ y, double *partials, double *dot_out,
                   unsigned *counter)
 {
-    __shared__ T tile[2][SP_TY + 2][SP_TX + 2];
-    const int i0 = blockIdx.x * SP_TX, j0 = blockIdx.y * SP_TY;
-    const int k0 = blockIdx.z * SP_KCHUNK;
-    const int k1 = min(g.nz, k0 + SP_KCHUNK);
-    const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
-    const bool act = i < g.nx && j < g.ny;
-    sp27_stage(tile[0], x, g, i0, j0, k0 - 1);
-    sp27_stage(tile[1], x, g, i0, j0, k0);
-    __syncthreads();
-    Plane9<T> pm = sp27_sums(tile[0]);
-    Plane9<T> p0 = sp27_sums(tile[1]);
+    constexpr int SP_TY = SpCfg<T>::TY, SP_R = SpCfg<T>::R;
+    constexpr int SP_H = SpCfg<T>::H, SP_NQ = SpCfg<T>::NQ;
+    __shared__ T pl[2][SP_H][SP_W];
+    const int tid = threadIdx.x;
+    const int id = (int)(blockIdx.x % 8) * t.per_xcd + (int)(blockIdx.x / 8);
     double acc = 0.0;
-    int buf = 0;
-    for (int k = k0; k < k1; ++k) {
-        __syncthreads();
-        sp27_stage(tile[buf], x, g, i0, j0, k + 1);
-        __syncthreads();
-        Plane9<T> pp = sp27_sums(tile[buf]);
-        buf ^= 1;
-        if (act) {
-            T nb = (pm.s9 + p0.s8) + pp.s9;
-            T v = fma(off, nb, diag * p0.c);
-            y[g.idx(i, j, k)] = v;
-            if (DOT) acc = fma((double)p0.c, (double)v, acc);
+    if (id < t.ntiles) {
+        const int tpl = t.nbx * t.nby;
+        const int layer = id / tpl, tile = id - layer * tpl;
+        const int i0 = (tile % t.nbx) * SP_TX, j0 = (tile / t.nbx) * SP_TY;
+        const int ka = layer * t.kc, kb = min(g.nz, ka + t.kc);
+        const int n = kb - ka;
+        const int64_t plane = (int64_t)g.nx * g.ny;
+
+        // staging slots of this thread: offset within a plane, -1 outside
+        // the grid (staged as 0), -2 no slot
+        int goff[SP_NQ];
+#pragma unroll
+        for (int q = 0; q < SP_NQ; ++q) {
+            const int e = tid + 256 * q;
+            goff[q] = -2;
+            if (e < SP_W * SP_H) {
+                const int row = e / SP_W, col = e - (e / SP_W) * SP_W;
+                const int i = i0 - 1 + col, j = j0 - 1 + row;
+                goff[q] = (i >= 0 && i < g.nx && j >= 0 && j < g.ny)
+                              ? j * g.nx + i
+                              : -1;
+            }
         }
-        pm = p0;
-        p0 = pp;
+        auto load = [&](T(&r)[SP_NQ], int k) {
+            const bool kin = k >= 0 && k < g.nz;
+            const T *xk = x + (int64_t)k * plane;
+#pragma unroll
+            for (int q = 0; q < SP_NQ; ++q)
+                r[q] = (kin && goff[q] >= 0) ? xk[goff[q]] : T(0);
+        };
+        auto store = [&](int b, const T(&r)[SP_NQ]) {
+            T *flat = &pl[b][0][0];
+#pragma unroll
+            for (int q = 0; q < SP_NQ; ++q)
+                if (goff[q] != -2) flat[tid + 256 * q] = r[q];
+        };
+        const int tx = tid & 63, ty = tid >> 6;
+        // 3x3 sums of the thread's SP_R rows in the plane staged in buffer b
+        auto sums = [&](int b, T(&s9)[SP_R], T(&s8)[SP_R], T(&c)[SP_R]) {
+            T rs[SP_R + 2], bb[SP_R];
+#pragma unroll
+            for (int rr = 0; rr < SP_R + 2; ++rr) {
+                const T *row = &pl[b][ty * SP_R + rr][tx];
+                const T xl = row[0], xc = row[1], xr = row[2];
+                rs[rr] = (xl + xc) + xr;
+                if (rr >= 1 && rr <= SP_R) {
+                    bb[rr - 1] = xl + xr;
+                    c[rr - 1] = xc;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < SP_R; ++r) {
+                s8[r] = (rs[r] + bb[r]) + rs[r + 2];
+                s9[r] = (rs[r] + (bb[r] + c[r])) + rs[r + 2];
+            }
+        };
+        const int i = i0 + tx;
+        // sums of the plane behind (p) and the current plane (s9c, s8c, cc)
+        T s9p[SP_R], s9c[SP_R], s8c[SP_R], cc[SP_R], d8[SP_R], dc[SP_R];
+        T ra[SP_NQ], rb[SP_NQ];
+        load(ra, ka - 1);
+        load(rb, ka);
+        store(0, ra);
+        load(ra, ka + 1);
+        __syncthreads();
+        sums(0, s9p, d8, dc);
+        store(1, rb);
+        if (n >= 2) load(rb, ka + 2);
+        __syncthreads();
+        sums(1, s9c, s8c, cc);
+        // one plane: stage plane k + 1 from r, prefetch k + 3 into r, sum
+        // the staged plane and write y at plane k
+        auto step = [&](T(&r)[SP_NQ], int s, int b) {
+            const int k = ka + s;
+            store(b, r);
+            if (s + 3 <= n) load(r, k + 3);
+            __syncthreads();
+            T s9n[SP_R], s8n[SP_R], cn[SP_R];
+            sums(b, s9n, s8n, cn);
+            T *yk = y + (int64_t)k * plane;
+#pragma unroll
+            for (int rr = 0; rr < SP_R; ++rr) {
+                const int j = j0 + ty * SP_R + rr;
+                if (i < g.nx && j < g.ny) {
+                    const T nb = (s9p[rr] + s8c[rr]) + s9n[rr];
+                    const T v = fma(off, nb, diag * cc[rr]);
+                    yk[j * g.nx + i] = v;
+                    if (DOT) acc = fma((double)cc[rr], (double)v, acc);
+                }
+                s9p[rr] = s9c[rr];
+                s9c[rr] = s9n[rr];
+                s8c[rr] = s8n[rr];
+                cc[rr] = cn[rr];
+            }
+        };
+        for (int s = 0; s < n; s += 2) {
+            step(ra, s, 0);
+            if (s + 1 < n) step(rb, s + 1, 1);
+        }
     }
     if (DOT) block_reduce_finish(acc, partials, dot_out, counter);
 }
@@ -577,12 +652,11 @@ static hipError_t sp27(const m2s_stencil &A, const void *x, void *y,
                        double *partials, double *out, hipStream_t s)
 {
     Grid g{A.ext.nx, A.ext.ny, A.ext.nz};
-    dim3 block(SP_TX, SP_TY);
-    dim3 grid((g.nx + SP_TX - 1) / SP_TX, (g.ny + SP_TY - 1) / SP_TY,
-              (g.nz + SP_KCHUNK - 1) / SP_KCHUNK);
-    if (DOT && (int64_t)grid.x * grid.y * grid.z > kRedBlocks) {
+    const SpTiles t = sp_tiles(g, SpCfg<T>::TY);
+    const dim3 block(256), grid(8 * t.per_xcd);
+    if (DOT && (int64_t)grid.x > kRedBlocks) {
         // too many blocks for the partials buffer: plain SpMV then a dot
-        hipLaunchKernelGGL((spmv27_kernel<T, false>), grid, block, 0, s, g,
+        hipLaunchKernelGGL((spmv27_kernel<T, false>), grid, block, 0, s, g, t,
                            (T)A.diag, (T)A.offdiag, (const T *)x, (T *)y,
                            nullptr, nullptr, nullptr);
         hipLaunchKernelGGL(dot_kernel, dim3(blocks_for(g.size(), 256,
@@ -592,7 +666,7 @@ static hipError_t sp27(const m2s_stencil &A, const void *x, void *y,
                            counter_of(partials));
         return hipGetLastError();
     }
-    hipLaunchKernelGGL((spmv27_kernel<T, DOT>), grid, block, 0, s, g,
+    hipLaunchKernelGGL((spmv27_kernel<T, DOT>), grid, block, 0, s, g, t,
                        (T)A.diag, (T)A.offdiag, (const T *)x, (T *)y,
                        partials, out, DOT ? counter_of(partials) : nullptr);
     return hipGetLastError();
