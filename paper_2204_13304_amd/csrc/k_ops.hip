@@ -10,7 +10,9 @@ namespace m2s {
 
 // Deterministic block reduction of one double per thread into partials[b];
 // the last block to finish sums the partials in index order into *out and
-// re-arms the counter.
+// re-arms the counter.  The partials are written and read at device scope
+// (coherent across the XCDs' L2s) and each block waits for its partial's
+// store before it counts itself in, so no cache-wide fence is needed.
 __device__ void block_reduce_finish(double v, double *partials, double *out,
                                     unsigned *counter)
 {
@@ -29,14 +31,15 @@ __device__ void block_reduce_finish(double v, double *partials, double *out,
         __syncthreads();
     }
     if (tid == 0) {
-        partials[bid] = red[0];
-        __threadfence();
+        __hip_atomic_store(partials + bid, red[0], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        // the partial is at the device coherence point before the count
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         unsigned prev = atomicAdd(counter, 1u);
         last = (prev == (unsigned)nb - 1);
     }
     __syncthreads();
     if (!last) return;
-    __threadfence();
     double acc = 0.0;
     for (int b = tid; b < nb; b += nt)
         acc += __hip_atomic_load(partials + b, __ATOMIC_RELAXED,
@@ -570,14 +573,29 @@ static unsigned *counter_of(double *partials)
     return (unsigned *)(partials + kRedBlocks);
 }
 
+// The grid-stride loops below load RED_U strides ahead before they
+// accumulate, in the same order as the plain loop, so that each thread has
+// several loads in flight (one at a time leaves the kernels latency-bound).
+constexpr int RED_U = 4;
+
 __global__ void __launch_bounds__(256)
     dot_kernel(const double *__restrict__ x, const double *__restrict__ y,
                int64_t n, double *partials, double *out, unsigned *counter)
 {
     double acc = 0.0;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x)
-        acc = fma(x[p], y[p], acc);
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; p + (RED_U - 1) * st < n; p += RED_U * st) {
+        double xv[RED_U], yv[RED_U];
+#pragma unroll
+        for (int u = 0; u < RED_U; ++u) {
+            xv[u] = x[p + u * st];
+            yv[u] = y[p + u * st];
+        }
+#pragma unroll
+        for (int u = 0; u < RED_U; ++u) acc = fma(xv[u], yv[u], acc);
+    }
+    for (; p < n; p += st) acc = fma(x[p], y[p], acc);
     block_reduce_finish(acc, partials, out, counter);
 }
 
@@ -587,8 +605,23 @@ __global__ void __launch_bounds__(256)
                     double *out, unsigned *counter)
 {
     double acc = 0.0;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; p + (RED_U - 1) * st < n; p += RED_U * st) {
+        double bv[RED_U], av[RED_U];
+#pragma unroll
+        for (int u = 0; u < RED_U; ++u) {
+            bv[u] = b[p + u * st];
+            av[u] = ax[p + u * st];
+        }
+#pragma unroll
+        for (int u = 0; u < RED_U; ++u) {
+            const double v = bv[u] - av[u];
+            r[p + u * st] = v;
+            acc = fma(v, v, acc);
+        }
+    }
+    for (; p < n; p += st) {
         const double v = b[p] - ax[p];
         r[p] = v;
         acc = fma(v, v, acc);
@@ -626,8 +659,27 @@ __global__ void __launch_bounds__(256)
         sc[SC_BD] = 1.0;
     }
     double acc = 0.0;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-         !skip && q < n; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (skip) q = n;
+    for (; q + (RED_U - 1) * st < n; q += RED_U * st) {
+        double xv[RED_U], pv[RED_U], rv[RED_U], av[RED_U];
+#pragma unroll
+        for (int u = 0; u < RED_U; ++u) {
+            xv[u] = x[q + u * st];
+            pv[u] = p[q + u * st];
+            rv[u] = r[q + u * st];
+            av[u] = ap[q + u * st];
+        }
+#pragma unroll
+        for (int u = 0; u < RED_U; ++u) {
+            x[q + u * st] = fma(alpha, pv[u], xv[u]);
+            const double v = fma(-alpha, av[u], rv[u]);
+            r[q + u * st] = v;
+            acc = fma(v, v, acc);
+        }
+    }
+    for (; q < n; q += st) {
         x[q] = fma(alpha, p[q], x[q]);
         const double v = fma(-alpha, ap[q], r[q]);
         r[q] = v;
