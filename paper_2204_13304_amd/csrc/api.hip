@@ -346,6 +346,19 @@ m2s_status half_sweep(const m2s_stencil &A, const Block7Consts *b7,
                                    *ws, P, s));
 }
 
+// The FP32 27-point backward half-sweep from xin, its result stored widened
+// to FP64 (the last sweep of a mixed-precision V-cycle).
+m2s_status half_sweep_wide(const m2s_stencil &A, const void *r,
+                           const void *xin, double *xout, m2s_workspace *ws,
+                           hipStream_t s)
+{
+    SweepPlan P{};
+    m2s_status st = make_plan(A, P, true);
+    if (st != M2S_OK) return st;
+    if ((st = ensure_tiles(ws, P.slab_planes / 4)) != M2S_OK) return st;
+    return hip_status(launch_sweep27_wide(A, r, xin, xout, *ws, P, s));
+}
+
 }  // namespace
 
 extern "C" {
@@ -938,19 +951,28 @@ struct m2s_mg {
 namespace {
 
 // z_l = V-cycle(r_l) on level l.
+// zwide (FP32 CONST27 levels only): the level's last sweep stores its
+// result widened to FP64 there instead of into z.
 m2s_status vcycle_level(m2s_mg *mg, int l, const void *r, void *z,
-                        hipStream_t s)
+                        hipStream_t s, double *zwide = nullptr)
 {
     MgLevel &lv = mg->L[l];
     m2s_status st;
+    const bool coarsest = l == mg->levels - 1;
+    auto last_bwd = [&]() -> m2s_status {
+        if (zwide)
+            return half_sweep_wide(lv.A, r, lv.ws->scratch, zwide, lv.ws, s);
+        return half_sweep(lv.A, nullptr, 1.0, r, lv.ws->scratch, z, true,
+                          false, lv.ws, s);
+    };
     // z = 0 followed by one SymGS: the forward half starts from zero
     if ((st = half_sweep(lv.A, nullptr, 1.0, r, nullptr, lv.ws->scratch,
                          false, true, lv.ws, s)) != M2S_OK)
         return st;
+    if (coarsest) return last_bwd();
     if ((st = half_sweep(lv.A, nullptr, 1.0, r, lv.ws->scratch, z, true,
                          false, lv.ws, s)) != M2S_OK)
         return st;
-    if (l == mg->levels - 1) return M2S_OK;
     MgLevel &cv = mg->L[l + 1];
     M2S_TRY(launch_restrict(lv.A, r, z, cv.r, s));
     if ((st = vcycle_level(mg, l + 1, cv.r, cv.z, s)) != M2S_OK) return st;
@@ -958,8 +980,7 @@ m2s_status vcycle_level(m2s_mg *mg, int l, const void *r, void *z,
     if ((st = half_sweep(lv.A, nullptr, 1.0, r, z, lv.ws->scratch, false,
                          false, lv.ws, s)) != M2S_OK)
         return st;
-    return half_sweep(lv.A, nullptr, 1.0, r, lv.ws->scratch, z, true, false,
-                      lv.ws, s);
+    return last_bwd();
 }
 
 }  // namespace
@@ -1068,8 +1089,13 @@ m2s_status m2s_mg_vcycle(m2s_mg *mg, const double *r, double *z,
     if (overlap(r, z, 8 * (size_t)n)) return M2S_ERR_ALIAS;
     if (mg->prec == M2S_F64) return vcycle_level(mg, 0, r, z, stream);
     M2S_TRY(launch_convert(r, M2S_F64, mg->r0, M2S_F32, n, stream));
-    m2s_status st = vcycle_level(mg, 0, mg->r0, mg->z0, stream);
-    if (st != M2S_OK) return st;
+    // the 27-point kernel's last sweep writes the FP64 z itself (its
+    // widened output uses 32-bit byte offsets); otherwise a conversion pass
+    const bool wide = mg->L[0].A.kind == M2S_CONST27 &&
+                      n * 8 < ((int64_t)1 << 31);
+    m2s_status st =
+        vcycle_level(mg, 0, mg->r0, mg->z0, stream, wide ? z : nullptr);
+    if (st != M2S_OK || wide) return st;
     return hip_status(launch_convert(mg->z0, M2S_F32, z, M2S_F64, n, stream));
 }
 

@@ -86,6 +86,7 @@ struct C27Args {
     const T *r;
     const T *xin;        // nullptr: start from zero
     T *xout;
+    double *xwide;       // WIDE: the FP32 sweep's output, widened to FP64
     T off, inv_diag;
     // ILU modes (see the kernel): per-point weight w = 1 / d, and the
     // constant diagonal of the factor sweep
@@ -121,7 +122,10 @@ __host__ __device__ inline int c27_slot(int ut, int vt, int KT, int nutb)
 //   1  ILU factor w = 1 / (diagc - off S)        (off = off^2, x is w)
 //   2  ILU lower  y = (r - off S) w
 //   3  ILU upper  z = r - off S w                (backward sweep, r = y)
-template <typename T, bool BWD, bool ZERO, int NW, int MODE>
+// WIDE (FP32 SymGS only): the finished values are stored widened to FP64
+// into xwide instead of xout -- the last sweep of a mixed-precision V-cycle
+// hands its result to the FP64 solver without a conversion pass.
+template <typename T, bool BWD, bool ZERO, int NW, int MODE, bool WIDE = false>
 __global__ void __launch_bounds__(64 * (2 * NW + 1))
     c27_tile_kernel(C27Args<T> a)
 {
@@ -277,9 +281,14 @@ __global__ void __launch_bounds__(64 * (2 * NW + 1))
             const __amdgpu_buffer_rsrc_t rs_x =
                 __builtin_amdgcn_make_buffer_rsrc(
                     (void *)(ZERO ? a.r : a.xin), 0, nbytes, 0x00020000);
+            static_assert(!WIDE || (sizeof(T) == 4 && MODE == 0),
+                          "widened output is for the FP32 SymGS sweep");
             const __amdgpu_buffer_rsrc_t rs_o =
-                __builtin_amdgcn_make_buffer_rsrc((void *)a.xout, 0, nbytes,
-                                                  0x00020000);
+                WIDE ? __builtin_amdgcn_make_buffer_rsrc(
+                           (void *)a.xwide, 0,
+                           (int)((unsigned)(last + 1) * 8u), 0x00020000)
+                     : __builtin_amdgcn_make_buffer_rsrc((void *)a.xout, 0,
+                                                         nbytes, 0x00020000);
             const __amdgpu_buffer_rsrc_t rs_w =
                 __builtin_amdgcn_make_buffer_rsrc(
                     (void *)(MODE >= 2 ? a.w : a.xout), 0,
@@ -320,7 +329,15 @@ __global__ void __launch_bounds__(64 * (2 * NW + 1))
                             rpipe[p8] = buf_load<T>(rs_r, boff(v, rb, cr + 8));
                         if constexpr (MODE >= 2)
                             wpipe[p8] = buf_load<T>(rs_w, boff(v, rb, cr + 8));
-                        buf_store<T, 0>(rs_o, boff(v, rb, cs), xv);
+                        if constexpr (WIDE)
+                            buf_store<double, 0>(
+                                rs_o,
+                                (v && (unsigned)cs < (unsigned)nx)
+                                    ? (unsigned)(rb + dir * cs) * 8u
+                                    : OOB,
+                                (double)xv);
+                        else
+                            buf_store<T, 0>(rs_o, boff(v, rb, cs), xv);
                     }
                     // -- old-value halo rows: u0 + 16, u0 + 17 of this
                     //    wavefront's planes (h < 8) and plane k0 + KT
@@ -464,11 +481,12 @@ size_t c27_lds_bytes(int nw, m2s_dtype t, int mode)
            es;
 }
 
-template <typename T, bool BWD, bool ZERO, int NW, int MODE = 0>
+template <typename T, bool BWD, bool ZERO, int NW, int MODE = 0,
+          bool WIDE = false>
 static hipError_t c27_launch_t(const C27Args<T> &a, int grid, size_t lds,
                                hipStream_t s)
 {
-    auto k = c27_tile_kernel<T, BWD, ZERO, NW, MODE>;
+    auto k = c27_tile_kernel<T, BWD, ZERO, NW, MODE, WIDE>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(
@@ -611,6 +629,47 @@ hipError_t launch_sweep27(const m2s_stencil &A, const void *r,
     a.bnd_elems = ws.bnd_elems;
     a.epoch = epoch;
     return c27_launch_dir(a, bwd, zero, nw, plan.grid, lds, s);
+}
+
+hipError_t launch_sweep27_wide(const m2s_stencil &A, const void *r,
+                               const void *xin, double *xout, Workspace &ws,
+                               const SweepPlan &plan, hipStream_t s)
+{
+    const int nw = plan.slab_planes / 4;
+    // the widened output is addressed with 32-bit byte offsets too
+    const int64_t n = (int64_t)A.ext.nx * A.ext.ny * A.ext.nz;
+    if (A.dtype != M2S_F32 || !xin || n * 8 >= (int64_t(1) << 31))
+        return hipErrorInvalidValue;
+    const size_t lds = c27_lds_bytes(nw, A.dtype, 0);
+    const uint64_t base = ws.ticket_base;
+    ws.ticket_base += (uint64_t)plan.nslabs + (uint64_t)plan.grid;
+    if (++ws.epoch == 0) ++ws.epoch;
+    C27Args<float> a{};
+    a.g = Grid{A.ext.nx, A.ext.ny, A.ext.nz};
+    a.ntiles = plan.nslabs;
+    a.nutb = ws.tile_nutb;
+    a.ns = ws.tile_ns;
+    a.tiles = ws.tile_list;
+    a.ticket = ws.ticket;
+    a.ticket_base = base;
+    a.err = ws.err;
+    const char *e = getenv("M2S_SPIN_LIMIT");
+    a.spin_limit = e ? std::max(1, atoi(e)) : (1 << 22);
+    a.r = (const float *)r;
+    a.xin = (const float *)xin;
+    a.xout = nullptr;
+    a.xwide = xout;
+    a.off = (float)A.offdiag;
+    a.inv_diag = (float)(1.0 / A.diag);
+    a.bnd = ws.bnd;
+    a.bnd_elems = ws.bnd_elems;
+    a.epoch = ws.epoch;
+    switch (nw) {
+    case 1: return c27_launch_t<float, true, false, 1, 0, true>(a, plan.grid, lds, s);
+    case 2: return c27_launch_t<float, true, false, 2, 0, true>(a, plan.grid, lds, s);
+    case 4: return c27_launch_t<float, true, false, 4, 0, true>(a, plan.grid, lds, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace m2s

@@ -273,6 +273,10 @@ hipError_t launch_sweep27(const m2s_stencil &A, const void *r,
                           const void *xin, void *xout, bool bwd,
                           Workspace &ws, const SweepPlan &plan,
                           hipStream_t s);
+// The FP32 backward sweep (from xin) storing its result widened to FP64.
+hipError_t launch_sweep27_wide(const m2s_stencil &A, const void *r,
+                               const void *xin, double *xout, Workspace &ws,
+                               const SweepPlan &plan, hipStream_t s);
 // Tiling of the 27-point sweep: tiles of 16 u = j + k by 4 * nw planes.
 struct C27Layout {
     int nw, kt, nbands, nutb, ns, wb;

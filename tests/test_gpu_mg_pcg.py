@@ -36,15 +36,25 @@ def test_vcycle_parity(m, shape, levels):
     assert rel_inf(z, ref) <= 1e-12
 
 
-def test_vcycle_f32(m):
-    shape = (32, 32, 32)
+@pytest.mark.parametrize("shape,levels", [((32, 32, 32), 3),
+                                          ((24, 40, 32), 1),
+                                          ((24, 40, 32), 2),
+                                          ((24, 40, 32), 3)])
+def test_vcycle_f32(m, shape, levels):
+    # the 27-point FP32 V-cycle's last sweep writes the FP64 z itself (the
+    # coarsest level's backward sweep when levels = 1): z holds FP32 values
+    # and matches the float oracle
+    banner(f"vcycle f32 {shape} levels {levels}")
     A = m.const27(shape)
-    mg = m.MG(A, 3, prec=torch.float32)
+    mg = m.MG(A, levels, prec=torch.float32)
     r = inputs.standard_normal(2, shape)
-    z = host(mg.vcycle(dev(r)))
-    ref32 = oracle.MG("const27", shape, 3, dtype=np.float32).vcycle(
+    zd = mg.vcycle(dev(r))
+    assert zd.dtype == torch.float64
+    z = host(zd)
+    assert np.array_equal(z, z.astype(np.float32).astype(np.float64))
+    ref32 = oracle.MG("const27", shape, levels, dtype=np.float32).vcycle(
         r.astype(np.float32))
-    ref64 = oracle.MG("const27", shape, 3).vcycle(r)
+    ref64 = oracle.MG("const27", shape, levels).vcycle(r)
     assert rel_inf(z, ref32) <= 1e-5
     assert rel_inf(z, ref64) <= 1e-5
 

@@ -372,3 +372,21 @@ def test_solve_128_against_oracle(m):
     print(f"[c5] sample rel errs {errs}", flush=True)
     for name, e in errs.items():
         assert e <= 1e-8, (name, e)
+
+
+def test_vcycle_f32(m):
+    """The VAR7 FP32 V-cycle (its FP64 output made by a conversion pass,
+    unlike the 27-point one) against the float oracle."""
+    shape = (16, 24, 32)
+    banner(f"var7 vcycle f32 {shape}")
+    pr = inputs.var7_problem(23, shape)
+    A = _A(m, pr)
+    mg = m.MG(A, 3, prec=torch.float32)
+    r = inputs.standard_normal(3, shape)
+    z = host(mg.vcycle(dev(r)))
+    faces = tuple(pr[k] for k in ("kx", "ky", "kz"))
+    ref32 = oracle.MG("var7", shape, 3, faces=faces,
+                      dtype=np.float32).vcycle(r.astype(np.float32))
+    ref64 = oracle.MG("var7", shape, 3, faces=faces).vcycle(r)
+    assert rel_inf(z, ref32) <= 1e-4
+    assert rel_inf(z, ref64) <= 1e-4
