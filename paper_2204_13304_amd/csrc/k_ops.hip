@@ -221,6 +221,12 @@ __global__ void __launch_bounds__(256)
     if (DOT) block_reduce_finish(acc, partials, dot_out, counter);
 }
 
+// The grid-stride loops of the reduction kernels load RED_U strides ahead
+// before they accumulate, in the same order as the plain loop, so that each
+// thread has several loads in flight (one at a time leaves them
+// latency-bound).
+constexpr int RED_U = 4;
+
 // --------------------------------------------------------------------------
 // VAR7 SpMV (optionally fused with x.y).
 // --------------------------------------------------------------------------
@@ -234,27 +240,44 @@ __global__ void __launch_bounds__(256)
     Faces F{g.nx, g.ny, g.nz};
     double acc = 0.0;
     const int64_t n = g.size();
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pl = (int64_t)g.nx * g.ny;
+    auto point = [&](int64_t p, T &xc, T &v) {
         const int i = (int)(p % g.nx);
         const int64_t t = p / g.nx;
         const int j = (int)(t % g.ny), k = (int)(t / g.ny);
         const T kxm = kx[F.ix(i, j, k)], kxp = kx[F.ix(i + 1, j, k)];
         const T kym = ky[F.iy(i, j, k)], kyp = ky[F.iy(i, j + 1, k)];
         const T kzm = kz[F.iz(i, j, k)], kzp = kz[F.iz(i, j, k + 1)];
-        const T xc = x[p];
+        xc = x[p];
         const T vmx = i > 0 ? x[p - 1] : T(0);
         const T vpx = i < g.nx - 1 ? x[p + 1] : T(0);
         const T vmy = j > 0 ? x[p - g.nx] : T(0);
         const T vpy = j < g.ny - 1 ? x[p + g.nx] : T(0);
-        const int64_t pl = (int64_t)g.nx * g.ny;
         const T vmz = k > 0 ? x[p - pl] : T(0);
         const T vpz = k < g.nz - 1 ? x[p + pl] : T(0);
         T d = ((kxm + kxp) + (kym + kyp)) + (kzm + kzp);
         T s1 = fma(kxm, vmx, kxp * vpx);
         T s2 = fma(kym, vmy, kyp * vpy);
         T s3 = fma(kzm, vmz, kzp * vpz);
-        T v = fma(d, xc, -((s1 + s2) + s3));
+        v = fma(d, xc, -((s1 + s2) + s3));
+    };
+    // RED_U points per trip, their loads ahead of the stores and of the
+    // accumulation (which keeps the plain loop's order)
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; p + (RED_U - 1) * st < n; p += RED_U * st) {
+        T xc[RED_U], v[RED_U];
+#pragma unroll
+        for (int u = 0; u < RED_U; ++u) point(p + u * st, xc[u], v[u]);
+#pragma unroll
+        for (int u = 0; u < RED_U; ++u) {
+            y[p + u * st] = v[u];
+            if (DOT) acc = fma((double)xc[u], (double)v[u], acc);
+        }
+    }
+    for (; p < n; p += st) {
+        T xc, v;
+        point(p, xc, v);
         y[p] = v;
         if (DOT) acc = fma((double)xc, (double)v, acc);
     }
@@ -572,11 +595,6 @@ static unsigned *counter_of(double *partials)
 {
     return (unsigned *)(partials + kRedBlocks);
 }
-
-// The grid-stride loops below load RED_U strides ahead before they
-// accumulate, in the same order as the plain loop, so that each thread has
-// several loads in flight (one at a time leaves the kernels latency-bound).
-constexpr int RED_U = 4;
 
 __global__ void __launch_bounds__(256)
     dot_kernel(const double *__restrict__ x, const double *__restrict__ y,
