@@ -310,8 +310,9 @@ m2s_status ensure_tiles(m2s_workspace *ws, int nw)
         ws->tile_nutb = L.njt;
         ws->tile_ns = L.ns;
     } else {
-        const B7Layout L = b7_layout(ws->g, nw);
+        B7Layout L = b7_layout(ws->g, nw);
         n = std::max<int64_t>(L.bnd_elems, 1);
+        tiles.swap(L.tiles);
         ws->tile_ntiles = L.ntiles;
         ws->tile_nutb = L.njt;
         ws->tile_ns = L.ns;

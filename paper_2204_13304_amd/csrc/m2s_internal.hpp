@@ -303,6 +303,7 @@ hipError_t launch_ilu0_apply(const m2s_stencil &A, const double *L,
 struct B7Layout {
     int nw, kt, njt, nbands, ntiles, ns, wb;
     int64_t bnd_elems;
+    std::vector<int2> tiles;  // (j-tile, k-tile) per ticket
 };
 B7Layout b7_layout(Grid g, int nw);
 size_t b7_lds_bytes(int nw);

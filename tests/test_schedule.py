@@ -334,8 +334,10 @@ def simulate_b7_tiles(shape, zero_start=False):
     KT = B7_KT
     njt = -(-ny // B7_TJ)
     nbands = -(-nz // KT)
-    ticket = {(jt, vt): vt * njt + jt for vt in range(nbands)
-              for jt in range(njt)}
+    # tickets in the order of the tiles' first steps j0 + k0, ties by k
+    order = sorted(((jt, vt) for vt in range(nbands) for jt in range(njt)),
+                   key=lambda t: (B7_TJ * t[0] + KT * t[1], t[1]))
+    ticket = {t: n for n, t in enumerate(order)}
     stored = {}
 
     def valid(j, k):
@@ -394,7 +396,7 @@ def simulate_b7_tiles(shape, zero_start=False):
                                    0 if first else old(hj, hk, ch), "mb"))
                 # poll
                 for e in range(5 * (KT + 16)):
-                    h = e // 5
+                    h = e % (KT + 16)   # records component-major
                     left = h < KT
                     jj, kk = (-1, h) if left else (h - KT, -1)
                     prod = (jt - 1, vt) if left else (jt, vt - 1)
