@@ -367,7 +367,9 @@ __global__ void __launch_bounds__(64 * (2 * NW + 1))
                         if (c < nx) {
                             typename R::V rec = ppipe[ph & (POLL - 1)];
                             const unsigned src = (unsigned)pslice(st) * RB;
+                            bool retried = false;
                             while (!R::ready(rec, ep)) {
+                                retried = true;
                                 if (--spin_budget < 0 ||
                                     __hip_atomic_load(
                                         a.err, __ATOMIC_RELAXED,
@@ -382,6 +384,14 @@ __global__ void __launch_bounds__(64 * (2 * NW + 1))
                                 rec = R::load(rs_b, src);
                             }
                             v = R::value(rec);
+                            // caught up: the slices preloaded before the
+                            // wait were loaded too early too; load them again
+                            if (retried) {
+#pragma unroll
+                                for (int q = 1; q < POLL; ++q)
+                                    ppipe[(ph + q) & (POLL - 1)] = R::load(
+                                        rs_b, (unsigned)pslice(st + q) * RB);
+                            }
                         }
                         hrow[c & (V7_W - 1)] = v;
                     }
