@@ -258,11 +258,15 @@ void m2s_mg_destroy(m2s_mg *mg);
  * MG (needs `mg` built on the same operator).  x holds x0 on entry and the
  * solution on return.  Synchronises `stream`.  Returns M2S_OK on
  * convergence (or after max_iter with rtol <= 0), M2S_ERR_NOT_CONVERGED,
- * M2S_ERR_BREAKDOWN, M2S_ERR_TIMEOUT.  Each iteration's scalars are read
- * back for the convergence and breakdown tests, except in a fixed-iteration
- * run (rtol <= 0) without history or residual replacement: there the host
- * does not wait per iteration, a breakdown (p.Ap <= 0 or a non-finite
- * scalar) is latched on the device and reported after the last iteration.
+ * M2S_ERR_BREAKDOWN, M2S_ERR_TIMEOUT.  The scalars are read back for the
+ * convergence and breakdown tests every check_every iterations (values
+ * <= 1 mean every iteration), at residual replacements and after the last
+ * iteration; a run with a history reads them every iteration, and a
+ * fixed-iteration run (rtol <= 0) without history or replacement only
+ * after the last one.  Between read-backs the host does not wait, and a
+ * breakdown (p.Ap <= 0 or a non-finite scalar) is latched on the device;
+ * a converged solve reports the first checked iteration that passes (at
+ * most check_every - 1 iterations past the first one that does).
  * Either way a breakdown leaves x at the last iterate before the failing
  * update (from that iteration on the update kernels leave x, r and p
  * alone) and iters is the iteration that broke down.
@@ -284,6 +288,7 @@ typedef struct {
     int max_iter;
     double rtol;
     int replace_every;
+    int check_every;   /* convergence read-back period; <= 1: every iteration */
 } m2s_pcg_opts;
 
 typedef struct {

@@ -34,7 +34,7 @@ class StencilC(C.Structure):
 
 class PcgOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("rtol", C.c_double),
-                ("replace_every", C.c_int)]
+                ("replace_every", C.c_int), ("check_every", C.c_int)]
 
 
 class PcgInfo(C.Structure):

@@ -306,17 +306,21 @@ class PcgWorkspace:
 
 def pcg_solve(A: Stencil, b, x=None, precond="mg", mg: MG | None = None,
               max_iter=50, rtol=0.0, replace_every=0, history=False,
-              raise_on_error=True, ws: PcgWorkspace | None = None):
+              raise_on_error=True, ws: PcgWorkspace | None = None,
+              check_every=1):
     """HPCG-form PCG; returns (x, info dict).  With a PcgWorkspace the solve
     allocates nothing (m2s_pcg_solve_ws); without one the library allocates
-    and frees the CG vectors inside the call (m2s_pcg_solve)."""
+    and frees the CG vectors inside the call (m2s_pcg_solve).  check_every:
+    the convergence test reads the residual back every that many
+    iterations."""
     lib = L.load()
     _need(b, torch.float64, A.shape, "b")
     if x is None:
         x = torch.zeros_like(b)
     _need(x, torch.float64, A.shape, "x")
     pc = {"none": L.PC_NONE, "symgs": L.PC_SYMGS, "mg": L.PC_MG}[precond]
-    opts = L.PcgOpts(int(max_iter), float(rtol), int(replace_every))
+    opts = L.PcgOpts(int(max_iter), float(rtol), int(replace_every),
+                     int(check_every))
     info = L.PcgInfo()
     hist = np.zeros(max_iter + 1) if history else None
     hp = hist.ctypes.data_as(C.c_void_p) if history else None

@@ -382,8 +382,8 @@ const char *m2s_status_string(m2s_status s)
 }
 
 // 2.0.0: m2s_ilu27_* renamed m2s_dilu27_*; m2s_ilu0_*, the PCG workspace
-// entry points and m2s_stream added
-int m2s_version(void) { return 20000; }
+// entry points and m2s_stream added; 2.1.0: m2s_pcg_opts.check_every
+int m2s_version(void) { return 20100; }
 
 m2s_status m2s_plan_sweep(const m2s_stencil *A, m2s_sweep_plan *plan)
 {
@@ -1209,6 +1209,7 @@ extern "C" m2s_status m2s_pcg_solve_ws(const m2s_stencil *A,
     double normr = normr0;
     m2s_status result = M2S_ERR_NOT_CONVERGED;
     const bool lazy = opts->rtol <= 0 && opts->replace_every <= 0 && !hist;
+    const int check_every = std::max(1, opts->check_every);
     int it = 0;
     if (hist) hist[0] = 1.0;
     if (!std::isfinite(normr0)) result = M2S_ERR_BREAKDOWN;
@@ -1241,10 +1242,16 @@ extern "C" m2s_status m2s_pcg_solve_ws(const m2s_stencil *A,
             M2S_TRY(launch_update_xr(x, B.r, B.p, B.ap, n, B.sc, B.partials,
                                      it, stream));
             // a fixed-iteration run without history or replacement has no
-            // test to make before its last iteration: the scalars stay on
-            // the device (a breakdown is latched there) and the host does
-            // not wait for each iteration
+            // test to make before its last iteration, and a convergence
+            // test runs only every check_every iterations: in between the
+            // scalars stay on the device (a breakdown is latched there) and
+            // the host does not wait for each iteration
             if (lazy && it < opts->max_iter) continue;
+            const bool replace_now =
+                opts->replace_every > 0 && it % opts->replace_every == 0;
+            if (!hist && !replace_now && it < opts->max_iter &&
+                it % check_every != 0)
+                continue;
             if ((st = fetch()) != M2S_OK) return st;
             const double pap = hsc[SC_PAP];
             normr = std::sqrt(hsc[SC_RR]);

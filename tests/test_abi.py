@@ -179,7 +179,7 @@ def test_pcg_workspace_argument_errors():
     s.dtype = L.F32
     assert lib.m2s_pcg_workspace_create(C.byref(s), C.byref(h)) == 3  # DTYPE
     s.dtype = L.F64
-    opts = L.PcgOpts(1, 0.0, 0)
+    opts = L.PcgOpts(1, 0.0, 0, 1)
     info = L.PcgInfo()
     P = C.c_void_p
     b, x = P(1 << 40), P((1 << 40) + 8 * 512)

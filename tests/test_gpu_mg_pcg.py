@@ -282,6 +282,36 @@ def test_pcg_workspace_reuse(m):
                     max_iter=2, ws=ws)
 
 
+@pytest.mark.parametrize("check_every", [3, 4, 7])
+def test_pcg_check_every(m, check_every):
+    # the convergence test every check_every iterations: the solve stops at
+    # the first checked iteration that passes, at most check_every - 1
+    # iterations past the every-iteration solve, and its x has the bits of
+    # a fixed-iteration run of that length (the same kernels run)
+    shape = (32, 24, 16)
+    banner(f"pcg check_every {check_every}")
+    A = m.const27(shape)
+    b = dev(oracle.spmv27(np.ones(shape)) +
+            inputs.rhs_perturbation(5, shape))
+    mg = m.MG(A, 3)
+    ws = m.PcgWorkspace(A)
+    x1, i1 = m.pcg_solve(A, b, None, "mg", mg, max_iter=100, rtol=1e-9,
+                         ws=ws)
+    xc, ic = m.pcg_solve(A, b, None, "mg", mg, max_iter=100, rtol=1e-9,
+                         ws=ws, check_every=check_every)
+    assert ic["iters"] % check_every == 0
+    assert i1["iters"] <= ic["iters"] <= i1["iters"] + check_every - 1
+    assert i1["true_rel_res"] <= 1e-9 and ic["true_rel_res"] <= 1e-9
+    xf, _ = m.pcg_solve(A, b, None, "mg", mg, max_iter=ic["iters"],
+                        rtol=0.0, ws=ws)
+    assert torch.equal(xc, xf)
+    # max_iter not a multiple: the last iteration is always checked
+    _, il = m.pcg_solve(A, b, None, "mg", mg, max_iter=check_every + 1,
+                        rtol=1e-30, ws=ws, check_every=check_every,
+                        raise_on_error=False)
+    assert il["iters"] == check_every + 1 and il["status"] == "M2S_ERR_NOT_CONVERGED"
+
+
 def test_pcg_breakdown_reported(m):
     shape = (8, 8, 8)
     A = m.const27(shape, diag=-26.0)
