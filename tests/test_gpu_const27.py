@@ -35,6 +35,37 @@ def test_spmv_parity(m, shape):
     assert np.array_equal(host(m.spmv(A, dev(ones))), oracle.spmv27(ones))
 
 
+# shapes around the SpMV tiling: 64 x 16 (x, y) tiles of layers of planes
+# (64 x 32 in FP32), ragged in x and y, one or two planes, several layers
+SPMV_SHAPES = [(3, 33, 130), (2, 17, 65), (64, 16, 64), (33, 48, 200),
+               (7, 95, 129)]
+
+
+@pytest.mark.parametrize("shape", SPMV_SHAPES)
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_spmv_tiling_edges(m, shape, dtype):
+    banner(f"spmv27 tiling {shape} {dtype}")
+    A = m.const27(shape, dtype=dtype)
+    x = inputs.standard_normal(6, shape)
+    y = host(m.spmv(A, dev(x, dtype)))
+    ref = oracle.spmv27(x.astype(np.float32).astype(np.float64)
+                        if dtype == torch.float32 else x)
+    assert rel_inf(y, ref) <= (1e-13 if dtype == torch.float64 else 2e-6)
+
+
+def test_pcg_on_a_wide_plane(m):
+    # a 1 x 1040 x 2048 grid has more SpMV tiles than the fused p.Ap's
+    # reduction partials hold, so the SpMV and the dot run as two kernels
+    shape = (1, 1040, 2048)
+    banner(f"pcg wide plane {shape}")
+    A = m.const27(shape)
+    b = inputs.standard_normal(7, shape)
+    x, info = m.pcg_solve(A, dev(b), None, "none", max_iter=4, rtol=0.0)
+    ref = oracle.pcg(b, precond="none", max_iter=4)
+    assert info["iters"] == ref["iters"] == 4
+    assert rel_inf(host(x), ref["x"]) <= 1e-12
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("direction", ["fwd", "bwd", "sym"])
 def test_symgs_parity_and_bitwise(m, shape, direction):
