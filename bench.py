@@ -245,17 +245,27 @@ def ilu_workload(torch, m, inputs, dev, reps):
     # ILU(0): the factor writes 27 coefficients per point (L 13, U 14) from
     # the neighbours' U rows; the apply reads L with r and y, then U with
     # y and z -- hyperplane by hyperplane, one launch per step
-    del ws, w
+    del w
     Lf, Uf = m.ilu0_factor(A)
     m.ilu0_apply(A, Lf, Uf, r, z)
     r0 = max(1, reps // 5)
     tf0 = event_ms(torch, lambda: m.ilu0_factor(A), r0)
     ta0 = event_ms(torch, lambda: m.ilu0_apply(A, Lf, Uf, r, z), r0)
+    # the band-wavefront solves on the packed factor
+    Lp, Up = m.ilu0_pack(A, Lf, Uf, ws)
+    tp0 = event_ms(torch, lambda: m.ilu0_pack(A, Lf, Uf, ws), 1)
+    del Lf, Uf
+    m.ilu0_apply_packed(A, Lp, Up, r, z, ws)
+    tb0 = event_ms(torch, lambda: m.ilu0_apply_packed(A, Lp, Up, r, z, ws),
+                   reps)
+    ws.check()
+    del Lp, Up, ws
     fb = (13 + 14) * 8 * n ** 3
     ab = (13 * 8 + 24 + 14 * 8 + 16) * n ** 3
     log(f"ilu0 256^3: factor {tf0:.3f} ms ({fb / (tf0 * 1e-3) / 1e9:.0f} "
         f"GB/s written), apply {ta0:.3f} ms "
-        f"({ab / (ta0 * 1e-3) / 1e9:.0f} GB/s)")
+        f"({ab / (ta0 * 1e-3) / 1e9:.0f} GB/s); band apply {tb0:.3f} ms "
+        f"({ab / (tb0 * 1e-3) / 1e9:.0f} GB/s), pack {tp0:.3f} ms")
     return {"dilu27": {
         "workload": "D-ILU (factored diagonal, off-diagonals of A kept) of "
                     "the 27-point 26/-1 operator at 256^3, FP64, r ~ N(0,1) "
@@ -266,9 +276,13 @@ def ilu_workload(torch, m, inputs, dev, reps):
         "apply_frac": gbs / HBM_PEAK_GBS},
         "ilu0_27": {
         "workload": "ILU(0) of the 27-point 26/-1 operator at 256^3, FP64, "
-                    "r ~ N(0,1) seed 52; hyperplane by hyperplane (1786 "
-                    "launches per pass)",
+                    "r ~ N(0,1) seed 52; factor and apply hyperplane by "
+                    "hyperplane (1786 launches per pass); band apply: "
+                    "persistent bands of 2 planes on the packed factor",
         "factor_ms": tf0, "apply_ms": ta0,
+        "band_apply_ms": tb0, "pack_ms": tp0,
+        "band_apply_achieved": ab / (tb0 * 1e-3) / 1e9,
+        "band_apply_frac": ab / (tb0 * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "factor_written_gbs": fb / (tf0 * 1e-3) / 1e9,
         "apply_achieved": ab / (ta0 * 1e-3) / 1e9,
         "apply_frac": ab / (ta0 * 1e-3) / 1e9 / HBM_PEAK_GBS,

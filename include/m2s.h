@@ -392,6 +392,35 @@ m2s_status m2s_ilu0_apply(const m2s_stencil *A, const double *L,
                           hipStream_t stream);
 
 /* ---------------------------------------------------------------------
+ * The same solves z = (L U)^{-1} r (Saad's ILU(0), Sec. 9) as persistent
+ * band wavefronts, for ny <= 512: a workgroup owns a band of kt planes
+ * (kt = min(nz, 512 / ny)), one lane per row, and walks it on the band's
+ * hyperplanes i + 2j + 4kk with an LDS ring of each row's last 8 new values;
+ * the band's top plane reaches the band above through epoch-tagged records
+ * in the workspace.  The upper solve runs on the mirrored grid.
+ * m2s_ilu0_pack copies the factor of m2s_ilu0_factor into the layout these
+ * solves read (caller-owned Lp of 13 n and Up of 14 n doubles: per plane
+ * and coefficient, the points of each diagonal i + 2j consecutive in j;
+ * Up holds 1 / u_pp in place of u_pp), once per factor.
+ * m2s_ilu0_apply_packed computes z from r with the packed factor: r is
+ * copied into the packed order and the solves' results kept there (the
+ * workspace's two scratch vectors: the upper solve's packed order is the
+ * lower one's reversed), z written back in natural order.  Results
+ * agree with m2s_ilu0_apply to rounding (ten of a point's 13 products are
+ * summed a step early, the rest added in the step; not bitwise).
+ * M2S_ERR_UNSUPPORTED for another kind or ny > 512, M2S_ERR_DTYPE for F32,
+ * M2S_ERR_SHAPE past 32-bit byte offsets (14 n doubles, or the records), M2S_ERR_ALIAS
+ * for overlapping arrays, M2S_ERR_TIMEOUT (via m2s_check) if a band waits
+ * past the spin limit.  A workspace serves one solve at a time.
+ * --------------------------------------------------------------------- */
+m2s_status m2s_ilu0_pack(const m2s_stencil *A, const double *L,
+                         const double *U, double *Lp, double *Up,
+                         m2s_workspace *ws, hipStream_t stream);
+m2s_status m2s_ilu0_apply_packed(const m2s_stencil *A, const double *Lp,
+                                 const double *Up, const double *r, double *z,
+                                 m2s_workspace *ws, hipStream_t stream);
+
+/* ---------------------------------------------------------------------
  * D-ILU of the 27-point operator (the factored-diagonal incomplete
  * factorisation: A's off-diagonals kept, only the diagonal factored; not
  * ILU(0), see above), CONST27 F64: M = (D + L) D^{-1} (D + U) with L, U the

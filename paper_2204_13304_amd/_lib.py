@@ -99,6 +99,8 @@ _SIGS = {
     "m2s_dilu27_apply": (C.c_int, [_S, _P, _P, _P, _P, _P]),
     "m2s_ilu0_factor": (C.c_int, [_S, _P, _P, _P]),
     "m2s_ilu0_apply": (C.c_int, [_S, _P, _P, _P, _P, _P]),
+    "m2s_ilu0_pack": (C.c_int, [_S, _P, _P, _P, _P, _P, _P]),
+    "m2s_ilu0_apply_packed": (C.c_int, [_S, _P, _P, _P, _P, _P, _P]),
     "m2s_dot": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
     "m2s_dot_noalloc": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
     "m2s_convert": (C.c_int, [_P, C.c_int, _P, C.c_int, C.c_int64, _P]),

@@ -414,6 +414,40 @@ def ilu0_apply(A: Stencil, Lf, Uf, r, z=None):
     return z
 
 
+def ilu0_pack(A: Stencil, Lf, Uf, ws: Workspace | None = None):
+    """The ILU(0) factor in the layout of the band-wavefront solves:
+    (Lp, Up), flat device arrays of 13 n and 14 n doubles."""
+    lib = L.load()
+    _need(Lf, A.dtype, A.field_shape + (13,), "L")
+    _need(Uf, A.dtype, A.field_shape + (14,), "U")
+    ws = ws or Workspace(A)
+    n = Lf.numel() // 13
+    Lp = torch.empty(13 * n, dtype=Lf.dtype, device=Lf.device)
+    Up = torch.empty(14 * n, dtype=Uf.dtype, device=Uf.device)
+    L.check(lib.m2s_ilu0_pack(A.ref(), _ptr(Lf), _ptr(Uf), _ptr(Lp),
+                              _ptr(Up), ws.handle, _stream()),
+            "m2s_ilu0_pack")
+    return Lp, Up
+
+
+def ilu0_apply_packed(A: Stencil, Lp, Up, r, z=None,
+                      ws: Workspace | None = None):
+    """z = (L U)^{-1} r by the band-wavefront solves (packed factor)."""
+    lib = L.load()
+    n = r.numel()
+    _need(Lp, A.dtype, (13 * n,), "Lp")
+    _need(Up, A.dtype, (14 * n,), "Up")
+    _need(r, A.dtype, A.field_shape, "r")
+    if z is None:
+        z = torch.empty_like(r)
+    _need(z, A.dtype, A.field_shape, "z")
+    ws = ws or Workspace(A)
+    L.check(lib.m2s_ilu0_apply_packed(A.ref(), _ptr(Lp), _ptr(Up), _ptr(r),
+                                      _ptr(z), ws.handle, _stream()),
+            "m2s_ilu0_apply_packed")
+    return z
+
+
 _AXES = {"x": 0, "y": 1, "z": 2}
 
 

@@ -96,6 +96,9 @@ struct m2s_workspace : public Workspace {
     // line-scheduled 27-point sweep: one 16-byte record per point, made on
     // the first such call (zeroed: epoch 0 is never a launch's)
     void *xl_rec = nullptr;
+    // band-wavefront ILU(0) solves: the packed layout's diagonal offsets
+    int *ilb_doff = nullptr;
+    int ilb_nd = 0;
 };
 
 namespace {
@@ -382,7 +385,8 @@ const char *m2s_status_string(m2s_status s)
 }
 
 // 2.0.0: m2s_ilu27_* renamed m2s_dilu27_*; m2s_ilu0_*, the PCG workspace
-// entry points and m2s_stream added; 2.1.0: m2s_pcg_opts.check_every
+// entry points and m2s_stream added; 2.1.0: m2s_pcg_opts.check_every,
+// m2s_ilu0_pack and m2s_ilu0_apply_packed
 int m2s_version(void) { return 20100; }
 
 m2s_status m2s_plan_sweep(const m2s_stencil *A, m2s_sweep_plan *plan)
@@ -458,6 +462,7 @@ void m2s_workspace_destroy(m2s_workspace *ws)
     if (ws->tile_list) (void)hipFree(ws->tile_list);
     if (ws->b7c) (void)hipFree(ws->b7c);
     if (ws->xl_rec) (void)hipFree(ws->xl_rec);
+    if (ws->ilb_doff) (void)hipFree(ws->ilb_doff);
     delete ws;
 }
 
@@ -564,6 +569,26 @@ m2s_status m2s_symgs_sequential(const m2s_stencil *A, const void *r, void *x,
     return M2S_OK;
 }
 
+namespace {
+// One 16-byte record per point (the x-line sweep; the band ILU(0) solves use
+// a part), made on the first such call and zeroed: epoch 0 is never a
+// launch's.
+m2s_status ensure_point_records(m2s_workspace *ws, uint64_t rec_bytes,
+                                hipStream_t stream)
+{
+    if (ws->xl_rec) return M2S_OK;
+    void *rec = nullptr;
+    if (hipMalloc(&rec, rec_bytes) != hipSuccess) return M2S_ERR_HIP;
+    // kept only once cleared: a later call relies on the zero epochs
+    if (hipMemsetAsync(rec, 0, rec_bytes, stream) != hipSuccess) {
+        (void)hipFree(rec);
+        return M2S_ERR_HIP;
+    }
+    ws->xl_rec = rec;
+    return M2S_OK;
+}
+}  // namespace
+
 m2s_status m2s_symgs_xline(const m2s_stencil *A, const void *r, void *x,
                            m2s_dir dir, m2s_workspace *ws, hipStream_t stream)
 {
@@ -580,16 +605,8 @@ m2s_status m2s_symgs_xline(const m2s_stencil *A, const void *r, void *x,
     if (rec_bytes >= (1ull << 32)) return M2S_ERR_SHAPE;
     const size_t vb = (size_t)npoints(*A) * elem_size(*A);
     if (overlap(r, x, vb)) return M2S_ERR_ALIAS;
-    if (!ws->xl_rec) {
-        void *rec = nullptr;
-        if (hipMalloc(&rec, rec_bytes) != hipSuccess) return M2S_ERR_HIP;
-        // kept only once cleared: a later call relies on the zero epochs
-        if (hipMemsetAsync(rec, 0, rec_bytes, stream) != hipSuccess) {
-            (void)hipFree(rec);
-            return M2S_ERR_HIP;
-        }
-        ws->xl_rec = rec;
-    }
+    if ((st = ensure_point_records(ws, rec_bytes, stream)) != M2S_OK)
+        return st;
     if (dir == M2S_SYM) {
         M2S_TRY(launch_xline_sweep(*A, r, x, ws->scratch, false, *ws,
                                    ws->xl_rec, stream));
@@ -768,6 +785,87 @@ m2s_status m2s_ilu0_apply(const m2s_stencil *A, const double *L,
         overlap2(U, (size_t)(14 * n) * 8, z, vb))
         return M2S_ERR_ALIAS;
     return hip_status(launch_ilu0_apply(*A, L, U, r, z, stream));
+}
+
+namespace {
+// checks shared by the packed ILU(0) entry points; the layout, its device
+// offset table in the workspace
+m2s_status ilb_prepare(const m2s_stencil *A, m2s_workspace *ws,
+                       IlbLayout &L)
+{
+    m2s_status st = validate(A);
+    if (st != M2S_OK) return st;
+    if (A->kind != M2S_CONST27) return M2S_ERR_UNSUPPORTED;
+    if (A->dtype != M2S_F64) return M2S_ERR_DTYPE;
+    if ((st = check_ws(*A, ws)) != M2S_OK) return st;
+    const Grid g{A->ext.nx, A->ext.ny, A->ext.nz};
+    L = ilb_layout(g);
+    if (L.kt == 0) return M2S_ERR_UNSUPPORTED;   // ny > 512
+    // packed arrays and records are addressed from 32-bit offsets
+    if (14 * 8 * npoints(*A) >= ((int64_t)1 << 31) ||
+        (int64_t)L.nbands * g.nx * g.ny * 16 >= ((int64_t)1 << 31) ||
+        L.lds > 160 * 1024 - 64)
+        return M2S_ERR_SHAPE;
+    const int nd = (int)L.doff.size();
+    if (ws->ilb_nd != nd || !ws->ilb_doff) {
+        if (ws->ilb_doff) {
+            if (hipDeviceSynchronize() != hipSuccess) return M2S_ERR_HIP;
+            (void)hipFree(ws->ilb_doff);
+            ws->ilb_doff = nullptr;
+            ws->ilb_nd = 0;
+        }
+        int *d = nullptr;
+        if (hipMalloc(&d, sizeof(int) * nd) != hipSuccess) return M2S_ERR_HIP;
+        if (hipMemcpy(d, L.doff.data(), sizeof(int) * nd,
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(d);
+            return M2S_ERR_HIP;
+        }
+        ws->ilb_doff = d;
+        ws->ilb_nd = nd;
+    }
+    return M2S_OK;
+}
+}  // namespace
+
+m2s_status m2s_ilu0_pack(const m2s_stencil *A, const double *L,
+                         const double *U, double *Lp, double *Up,
+                         m2s_workspace *ws, hipStream_t stream)
+{
+    IlbLayout lay;
+    m2s_status st = ilb_prepare(A, ws, lay);
+    if (st != M2S_OK) return st;
+    if (!L || !U || !Lp || !Up) return M2S_ERR_ARG;
+    const int64_t n = npoints(*A);
+    const size_t lb = (size_t)(13 * n) * 8, ub = (size_t)(14 * n) * 8;
+    if (overlap2(Lp, lb, Up, ub) || overlap2(L, lb, Lp, lb) ||
+        overlap2(L, lb, Up, ub) || overlap2(U, ub, Lp, lb) ||
+        overlap2(U, ub, Up, ub))
+        return M2S_ERR_ALIAS;
+    return hip_status(launch_ilu0_pack(*A, ws->ilb_doff, L, U, Lp, Up, stream));
+}
+
+m2s_status m2s_ilu0_apply_packed(const m2s_stencil *A, const double *Lp,
+                                 const double *Up, const double *r, double *z,
+                                 m2s_workspace *ws, hipStream_t stream)
+{
+    IlbLayout lay;
+    m2s_status st = ilb_prepare(A, ws, lay);
+    if (st != M2S_OK) return st;
+    if (!Lp || !Up || !r || !z) return M2S_ERR_ARG;
+    const int64_t n = npoints(*A);
+    const size_t vb = 8 * (size_t)n;
+    if (overlap(r, z, vb) || overlap2(Lp, (size_t)(13 * n) * 8, z, vb) ||
+        overlap2(Up, (size_t)(14 * n) * 8, z, vb))
+        return M2S_ERR_ALIAS;
+    if ((st = ensure_point_records(ws, 16ull * (uint64_t)n, stream)) !=
+        M2S_OK)
+        return st;
+    const int64_t rec_elems =
+        (int64_t)lay.nbands * A->ext.nx * A->ext.ny;
+    return hip_status(launch_ilu0_apply_packed(
+        *A, lay, ws->ilb_doff, Lp, Up, r, (double *)ws->scratch,
+        (double *)ws->scratch2, z, *ws, ws->xl_rec, rec_elems, stream));
 }
 
 m2s_status m2s_penta_lines(int32_t nx, int32_t ny, int32_t nz, int32_t axis,

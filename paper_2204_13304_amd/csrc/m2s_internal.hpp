@@ -299,6 +299,23 @@ hipError_t launch_ilu0_factor(const m2s_stencil &A, double *L, double *U,
 hipError_t launch_ilu0_apply(const m2s_stencil &A, const double *L,
                              const double *U, const double *r, double *z,
                              hipStream_t s);
+// The band-wavefront solves: bands of kt planes (ny * kt <= 512 rows, one
+// lane each), coefficients packed by the band's steps (k_ilu0.hip).
+struct IlbLayout {
+    int kt = 0, nbands = 0, nsteps = 0, threads = 0;  // kt = 0: ny > 512
+    size_t lds = 0;
+    std::vector<int> doff;   // first packed index of each plane diagonal
+};
+IlbLayout ilb_layout(const Grid &g);
+hipError_t launch_ilu0_pack(const m2s_stencil &A, const int *doff,
+                            const double *L, const double *U, double *Lp,
+                            double *Up, hipStream_t s);
+hipError_t launch_ilu0_apply_packed(const m2s_stencil &A, const IlbLayout &L,
+                                    const int *doff, const double *Lp,
+                                    const double *Up, const double *r,
+                                    double *y, double *t, double *z,
+                                    Workspace &ws, void *rec,
+                                    int64_t rec_elems, hipStream_t s);
 // Tiling of the block SSOR sweep: rectangular tiles of 16 j by 4 * nw k.
 struct B7Layout {
     int nw, kt, njt, nbands, ntiles, ns, wb;

@@ -243,3 +243,60 @@ def test_ilu0_rejects_other_kinds_and_aliasing(m):
     r = dev(np.ones((4, 4, 4)))
     with pytest.raises(RuntimeError, match="M2S_ERR_ALIAS"):
         m.ilu0_apply(A, Lg, Ug, r, r)
+
+
+ILB_SHAPES = [(9, 13, 17), (20, 5, 33), (1, 1, 1), (3, 64, 10),
+              (16, 16, 16), (5, 300, 7), (4, 512, 3), (11, 100, 9),
+              (2, 2, 130)]
+
+
+@pytest.mark.parametrize("shape", ILB_SHAPES)
+def test_ilu0_band_apply(m, shape):
+    # the band-wavefront solves (bands of 512 / ny planes, records between
+    # bands) against the oracle's ILU(0) solve; twice in a row on one
+    # workspace, and beside the hyperplane solves
+    banner(f"ilu0 band {shape}")
+    A = m.const27(shape)
+    ws = m.Workspace(A)
+    Lg, Ug = m.ilu0_factor(A)
+    Lp, Up = m.ilu0_pack(A, Lg, Ug, ws)
+    r = inputs.standard_normal(56, shape)
+    z = m.ilu0_apply_packed(A, Lp, Up, dev(r), ws=ws)
+    ws.check()
+    Lo, Uo = oracle.ilu0_27_factor(shape)
+    assert rel_inf(host(z), oracle.ilu0_27_solve(Lo, Uo, r)) <= 1e-13
+    z2 = m.ilu0_apply_packed(A, Lp, Up, dev(r), ws=ws)
+    ws.check()
+    assert torch.equal(z, z2)
+    zh = m.ilu0_apply(A, Lg, Ug, dev(r))
+    assert rel_inf(host(zh), host(z)) <= 1e-13
+
+
+def test_ilu0_band_full_size_256(m):
+    shape = (256, 256, 256)
+    banner("ilu0 band 256^3")
+    A = m.const27(shape)
+    ws = m.Workspace(A)
+    Lg, Ug = m.ilu0_factor(A)
+    Lp, Up = m.ilu0_pack(A, Lg, Ug, ws)
+    del Lg, Ug
+    r = inputs.standard_normal(57, shape)
+    z = m.ilu0_apply_packed(A, Lp, Up, dev(r), ws=ws)
+    ws.check()
+    Lo, Uo = oracle.ilu0_27_factor(shape)
+    assert rel_inf(host(z), oracle.ilu0_27_solve(Lo, Uo, r)) <= 1e-13
+
+
+def test_ilu0_band_rejects(m):
+    A = m.const27((2, 513, 3))   # ny > 512: no band kernel
+    ws = m.Workspace(A)
+    Lg, Ug = m.ilu0_factor(A)
+    with pytest.raises(RuntimeError, match="M2S_ERR_UNSUPPORTED"):
+        m.ilu0_pack(A, Lg, Ug, ws)
+    B = m.const27((4, 4, 4))
+    wb = m.Workspace(B)
+    Lg, Ug = m.ilu0_factor(B)
+    Lp, Up = m.ilu0_pack(B, Lg, Ug, wb)
+    r = dev(np.ones((4, 4, 4)))
+    with pytest.raises(RuntimeError, match="M2S_ERR_ALIAS"):
+        m.ilu0_apply_packed(B, Lp, Up, r, r, ws=wb)
