@@ -41,6 +41,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 namespace m2s {
 
@@ -294,7 +295,13 @@ __global__ void __launch_bounds__(B7_NT)
         // backward sweep, the 5 components of a point never do).  Rows
         // outside the grid get kc far below 0, so every column test fails
         // and their loads read 0; their ring slots hold 0.
-        const bool xw = role == R_XMEM;
+        // The x and the b wavefronts run separate instantiations of one
+        // loop: sharing one loop (and its staging registers) behind a
+        // branch on the role made the compiler wait, in every step, for
+        // the loads the other role would have issued in the step before,
+        // which undid the 8-step prefetch.
+        auto mem_role = [&](auto xw_tag) {
+        constexpr bool xw = decltype(xw_tag)::value;
         const __amdgpu_buffer_rsrc_t rs_x = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(a.xin ? a.xin : a.b), 0, a.xin ? nbytes : 0, 0x00020000);
         const __amdgpu_buffer_rsrc_t rs_bb = __builtin_amdgcn_make_buffer_rsrc(
@@ -362,7 +369,7 @@ __global__ void __launch_bounds__(B7_NT)
                     const int p = s8 & 3, h = s8 >> 2;
                     const int st = Tb + ph0 + s8;
                     const bool pin_k = k0 + p < nz;
-                    if (xw) {
+                    if constexpr (xw) {
                         // store [f - 4, f), then stage [f + 4, f + 8)
 #pragma unroll
                         for (int q = 0; q < 5; ++q) {
@@ -430,6 +437,11 @@ __global__ void __launch_bounds__(B7_NT)
                 if (s_abort) break;
             }
         }
+        };
+        if (role == R_XMEM)
+            mem_role(std::true_type{});
+        else
+            mem_role(std::false_type{});
     } else {
         // ====== poll wavefront: records l and l + 64 of the halo ======
         // halo row h < KT: (jj = -1, kk = h) from tile (jt - 1, vt), entry h;
