@@ -49,9 +49,12 @@ constexpr int B7_TJ = 16;    // j-rows per tile
 constexpr int B7_KT = 4;     // planes per tile
 constexpr int B7_RJ = 18;    // x-ring rows per plane: jj = -1 .. 16
 constexpr int B7_W = 16;     // x-ring columns
-constexpr int B7_RS = 81;    // x-ring row stride (doubles): 16 x 5 + 1
-constexpr int B7_BS = 41;    // b ring: 8 columns x 5 + 1
-constexpr int B7_US = 21;    // u and g rings: 4 columns x 5 + 1
+// Ring row strides (doubles), unpadded: the rows' column skew already
+// spreads a step's accesses, and with 64 banks an odd padding put three
+// lanes of a 32-lane pass on one bank of the x ring
+constexpr int B7_RS = 80;    // x ring: 16 columns x 5
+constexpr int B7_BS = 40;    // b ring: 8 columns x 5
+constexpr int B7_US = 20;    // u and g rings: 4 columns x 5
 constexpr int B7_POLL = 1;   // boundary poll distance (steps): a step here
                              // lasts about half a record round trip, and a
                              // consumer settles about POLL steps plus a
