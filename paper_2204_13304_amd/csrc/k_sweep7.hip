@@ -49,16 +49,21 @@ constexpr int B7_TJ = 16;    // j-rows per tile
 constexpr int B7_KT = 4;     // planes per tile
 constexpr int B7_RJ = 18;    // x-ring rows per plane: jj = -1 .. 16
 constexpr int B7_W = 16;     // x-ring columns
-// Ring row strides (doubles), unpadded: the rows' column skew already
-// spreads a step's accesses, and with 64 banks an odd padding put three
-// lanes of a 32-lane pass on one bank of the x ring
+// Ring row strides (doubles).  The rows' column skew spreads a step's
+// accesses over the banks by itself, so the x and b rings are unpadded (a
+// padding of one double put three lanes on one bank); the 4-column u and g
+// rings are padded by 2 (unpadded: four lanes on one bank, now two).
 constexpr int B7_RS = 80;    // x ring: 16 columns x 5
 constexpr int B7_BS = 40;    // b ring: 8 columns x 5
-constexpr int B7_US = 20;    // u and g rings: 4 columns x 5
-constexpr int B7_POLL = 1;   // boundary poll distance (steps): a step here
-                             // lasts about half a record round trip, and a
-                             // consumer settles about POLL steps plus a
-                             // round trip behind its neighbour
+constexpr int B7_US = 22;    // u and g rings: 4 columns x 5, + 2
+// Boundary poll distance (steps) and the ring of registers the polled
+// records wait in.  A consumer settles about POLL steps plus a record round
+// trip behind its neighbour, and the poll wavefront waits, every step, for
+// the record it loaded POLL steps earlier.
+constexpr int B7_POLL = 1;
+constexpr int B7_PRING = 1;  // a power of 2 dividing the 4-step unroll
+static_assert(B7_POLL <= B7_PRING && 4 % B7_PRING == 0,
+              "a polled slot is checked before it is reloaded");
 constexpr int B7_PRE = 20;   // steps before the smallest row skew
 constexpr int B7_NT = 384;   // six wavefronts
 // Role of wavefront w.  The arithmetic roles issue the most instructions
@@ -450,9 +455,9 @@ __global__ void __launch_bounds__(B7_NT)
         // halo row h < KT: (jj = -1, kk = h) from tile (jt - 1, vt), entry h;
         // h = KT + jj: plane k0 - 1 row jj from (jt, vt - 1), entry KT + jj
         // (jj < 15) or KT - 1 (jj = 15)
-        typename R::V ppipe[B7_POLL][2];
+        typename R::V ppipe[B7_PRING][2];
 #pragma unroll
-        for (int p = 0; p < B7_POLL; ++p) ppipe[p][0] = ppipe[p][1] = R::V{};
+        for (int p = 0; p < B7_PRING; ++p) ppipe[p][0] = ppipe[p][1] = R::V{};
         int spin_budget = a.spin_limit;
         while (next_tile()) {
             int hs[2], hslot[2], hT0[2], hx[2];
@@ -493,10 +498,12 @@ __global__ void __launch_bounds__(B7_NT)
                         if (hv[q] && c >= 0) {
                             double v = 0.0;
                             if (c < nx) {
-                                typename R::V r = ppipe[ph & (B7_POLL - 1)][q];
+                                typename R::V r = ppipe[ph & (B7_PRING - 1)][q];
                                 const unsigned src =
                                     (unsigned)pslice(q, st) * RB;
+                                bool retried = false;
                                 while (!R::ready(r, ep)) {
+                                    retried = true;
                                     if (--spin_budget < 0 ||
                                         __hip_atomic_load(
                                             a.err, __ATOMIC_RELAXED,
@@ -512,10 +519,20 @@ __global__ void __launch_bounds__(B7_NT)
                                     r = R::load(rs_b, src);
                                 }
                                 v = R::value(r);
+                                // the consumer has caught up: the records
+                                // preloaded before the wait are stale too
+                                if (retried) {
+#pragma unroll
+                                    for (int d = 1; d < B7_POLL; ++d)
+                                        ppipe[(ph + d) & (B7_PRING - 1)][q] =
+                                            R::load(rs_b,
+                                                    (unsigned)pslice(q, st + d) *
+                                                        RB);
+                                }
                             }
                             xr[hx[q] + (c & (B7_W - 1)) * 5] = v;
                         }
-                        ppipe[ph & (B7_POLL - 1)][q] = R::load(
+                        ppipe[(ph + B7_POLL) & (B7_PRING - 1)][q] = R::load(
                             rs_b, hv[q] ? (unsigned)pslice(q, st + B7_POLL) * RB
                                         : OOB);
                     }
