@@ -20,12 +20,13 @@
 //   1 upper     u(f + 2) = b - sum_upper B_d x_d (old values: the upper
 //               neighbours reach column f + 2 only after this step)
 //   2 relax     g(f + 1) = (1 - w) x_old(f + 1) + G u(f + 1)
-//   3 x memory  stages x_old windows [f + 4, f + 8), stores [f - 4, f)
-//               (loads are parked in registers for 8 steps, two services
-//               of the plane, to cover the memory latency)
+//   3 x memory  stages x_old windows [f + 4, f + 8) (loads are parked in
+//               registers for 8 steps, two services of the plane, to cover
+//               the memory latency)
 //   4 poll      the neighbour tiles' boundary records (new values)
 //   5 b memory  stages b windows [f + 3, f + 7) and the old values of the
 //               halo rows (row 16 of every plane, plane 4)
+//   6 x stores  stores the finished columns [f - 4, f)
 // The memory wavefronts serve the 4 planes in turn, one per step, with
 // 4-column windows (element l + 64q -> row (l + 64q) / 20, column
 // ((l + 64q) % 20) / 5, component (l + 64q) % 5).  Every role runs the same
@@ -65,12 +66,13 @@ constexpr int B7_PRING = 1;  // a power of 2 dividing the 4-step unroll
 static_assert(B7_POLL <= B7_PRING && 4 % B7_PRING == 0,
               "a polled slot is checked before it is reloaded");
 constexpr int B7_PRE = 20;   // steps before the smallest row skew
-constexpr int B7_NT = 384;   // six wavefronts
-// Role of wavefront w.  The arithmetic roles issue the most instructions
-// per step; wavefronts w and w + 4 share a SIMD, so compute and upper get a
-// SIMD each and the lighter roles go in pairs (b memory + poll, x memory +
-// relax).
-enum { R_COMPUTE, R_UPPER, R_RELAX, R_XMEM, R_POLL, R_BMEM };
+constexpr int B7_NT = 448;   // seven wavefronts
+// Role of wavefront w.  Wavefronts w and w + 4 share a SIMD: upper, which
+// issues the most instructions per step, gets a SIMD of its own, compute
+// shares one with the x stores (measured 1 % faster than the other way
+// round), and the other light roles go in pairs (b memory + poll, x memory
+// + relax).
+enum { R_COMPUTE, R_UPPER, R_RELAX, R_XMEM, R_POLL, R_BMEM, R_XST };
 __device__ constexpr int b7_role(int w)
 {
     return w == 0 ? R_BMEM
@@ -78,7 +80,8 @@ __device__ constexpr int b7_role(int w)
          : w == 2 ? R_COMPUTE
          : w == 3 ? R_UPPER
          : w == 4 ? R_POLL
-                  : R_RELAX;
+         : w == 5 ? R_RELAX
+                  : R_XST;
 }
 
 namespace {
@@ -294,7 +297,7 @@ __global__ void __launch_bounds__(B7_NT)
                 }
             }
         }
-    } else if (role == R_XMEM || role == R_BMEM) {
+    } else if (role == R_XMEM || role == R_BMEM || role == R_XST) {
         // ====== memory wavefronts ======
         // Per plane p (served at steps T with (T - T_start) mod 4 = p) and
         // element q the step-independent parts of the addresses: column
@@ -303,13 +306,17 @@ __global__ void __launch_bounds__(B7_NT)
         // backward sweep, the 5 components of a point never do).  Rows
         // outside the grid get kc far below 0, so every column test fails
         // and their loads read 0; their ring slots hold 0.
-        // The x and the b wavefronts run separate instantiations of one
-        // loop: sharing one loop (and its staging registers) behind a
-        // branch on the role made the compiler wait, in every step, for
-        // the loads the other role would have issued in the step before,
-        // which undid the 8-step prefetch.
-        auto mem_role = [&](auto xw_tag) {
-        constexpr bool xw = decltype(xw_tag)::value;
+        // The x staging, x store and b wavefronts run separate
+        // instantiations of one loop (KIND 0, 1, 2): sharing one loop (and
+        // its staging registers) behind a branch on the role made the
+        // compiler wait, in every step, for the loads the other role would
+        // have issued in the step before, which undid the 8-step prefetch.
+        // The stores have a wavefront of their own because a wavefront keeps
+        // at most 63 memory instructions in flight: with the stores, the x
+        // staging loads could run only about 6 steps ahead.
+        auto mem_role = [&](auto kind_tag) {
+        constexpr int KIND = decltype(kind_tag)::value;
+        constexpr bool xw = KIND != 2;
         const __amdgpu_buffer_rsrc_t rs_x = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(a.xin ? a.xin : a.b), 0, a.xin ? nbytes : 0, 0x00020000);
         const __amdgpu_buffer_rsrc_t rs_bb = __builtin_amdgcn_make_buffer_rsrc(
@@ -378,7 +385,9 @@ __global__ void __launch_bounds__(B7_NT)
                     const int st = Tb + ph0 + s8;
                     const bool pin_k = k0 + p < nz;
                     if constexpr (xw) {
-                        // store [f - 4, f), then stage [f + 4, f + 8)
+                        // store [f - 4, f) (KIND 1), stage [f + 4, f + 8)
+                        // (KIND 0)
+                        if constexpr (KIND == 1) {
 #pragma unroll
                         for (int q = 0; q < 5; ++q) {
                             const int kc = pin_k ? kc0[q] - p : NOFF;
@@ -392,6 +401,7 @@ __global__ void __launch_bounds__(B7_NT)
                                      : OOB,
                                  xv);
                         }
+                        } else {
 #pragma unroll
                         for (int q = 0; q < 5; ++q) {
                             const int kc = pin_k ? kc0[q] - p : NOFF;
@@ -404,6 +414,7 @@ __global__ void __launch_bounds__(B7_NT)
                                 rs_x, (unsigned)cl < (unsigned)nx
                                           ? (unsigned)(gb + dir * 5 * cl) * 8u
                                           : OOB);
+                        }
                         }
                     } else {
                         // stage b [f + 3, f + 7)
@@ -447,9 +458,11 @@ __global__ void __launch_bounds__(B7_NT)
         }
         };
         if (role == R_XMEM)
-            mem_role(std::true_type{});
+            mem_role(std::integral_constant<int, 0>{});
+        else if (role == R_XST)
+            mem_role(std::integral_constant<int, 1>{});
         else
-            mem_role(std::false_type{});
+            mem_role(std::integral_constant<int, 2>{});
     } else {
         // ====== poll wavefront: records l and l + 64 of the halo ======
         // halo row h < KT: (jj = -1, kk = h) from tile (jt - 1, vt), entry h;

@@ -324,7 +324,7 @@ struct B7Layout {
 };
 B7Layout b7_layout(Grid g, int nw);
 size_t b7_lds_bytes(int nw);
-int b7_threads(int nw);  // nw compute + 2 nw memory + 1 poll wavefronts
+int b7_threads(int nw);  // seven wavefronts, one per role
 hipError_t launch_sweep7(const m2s_stencil &A, const Block7Consts &C,
                          double omega, const void *b, const void *xin,
                          void *xout, bool bwd, Workspace &ws,

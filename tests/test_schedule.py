@@ -316,12 +316,14 @@ def test_c27_plan_matches_tile_model(shape, monkeypatch):
 
 # ---------------------------------------------------------------------------
 # Model of the tiled block-SSOR sweep kernel (7-point, 5 components): tiles
-# of 16 j by 4 k, six roles -- compute (x at the front f from g(f) and the
+# of 16 j by 4 k, seven roles -- compute (x at the front f from g(f) and the
 # new values of the lower neighbours), upper (u at f + 2 from b and the old
 # values of the upper neighbours), relax (g at f + 1 from u and the old
-# value), x memory (stores [f - 4, f), stages x_old [f + 4, f + 8)), b
-# memory (stages b [f + 3, f + 7) and the old values of the halo rows),
-# poll.  Rings: x 16 columns, b 8, u and g 4.  Values are tracked per
+# value), x memory (stages x_old [f + 4, f + 8)), x stores (stores
+# [f - 4, f)), b memory (stages b [f + 3, f + 7) and the old values of the
+# halo rows), poll.  The two x roles run in the same step, one reading the
+# slots of [f - 4, f), the other writing those of [f + 4, f + 8), so the
+# model treats them as one.  Rings: x 16 columns, b 8, u and g 4.  Values are tracked per
 # (row, column) with all 5 components together.  As above, a slot written
 # by one wavefront in a step must not be touched by another in that step,
 # and every read a later value depends on must see the right value.
@@ -488,8 +490,8 @@ def test_b7_plan_matches_tile_model(shape):
     import paper_2204_13304_amd as m
     p = m.plan_sweep(m.block7(shape, np.eye(5)[None].repeat(7, 0) * 10))
     assert p["slab_planes"] == B7_KT
-    # compute, upper, relax, x memory, poll, b memory
-    assert p["threads"] == 64 * 6
+    # compute, upper, relax, x memory, poll, b memory, x stores
+    assert p["threads"] == 64 * 7
     assert p["nslabs"] == b7_tile_count(shape)
 
 
