@@ -52,8 +52,9 @@ constexpr int B7_RJ = 18;    // x-ring rows per plane: jj = -1 .. 16
 constexpr int B7_W = 16;     // x-ring columns
 // Ring row strides (doubles).  The rows' column skew spreads a step's
 // accesses over the banks by itself, so the x and b rings are unpadded (a
-// padding of one double put three lanes on one bank); the 4-column u and g
-// rings are padded by 2 (unpadded: four lanes on one bank, now two).
+// padding of one double put four lanes of a 16-lane pass of a 64-bit access
+// on one pair of banks); the 4-column u and g rings are padded by 2
+// (unpadded: four lanes on one pair, now two).
 constexpr int B7_RS = 80;    // x ring: 16 columns x 5
 constexpr int B7_BS = 40;    // b ring: 8 columns x 5
 constexpr int B7_US = 22;    // u and g rings: 4 columns x 5, + 2
