@@ -237,41 +237,66 @@ __host__ __device__ inline int ilb_jmin(int d, int nx)
 
 }  // namespace
 
+// Packed position q of a plane -> (d, j): the diagonal d is the last one
+// whose offset is <= q (doff ascends; empty diagonals share the offset of
+// the next one), j = jmin(d) + q - doff[d].
+__device__ inline void ilb_locate(const int *__restrict__ doff, int nd,
+                                  int nx, int q, int &d, int &j)
+{
+    int lo = 0, hi = nd - 1;  // doff[lo] <= q < doff[hi] (doff[nd-1] = plane)
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (doff[mid] <= q)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    d = lo;
+    j = ilb_jmin(lo, nx) + (q - doff[lo]);
+}
+
 // Packed coefficient arrays: Lp holds 13 arrays of n doubles per plane
 // block, Up 14 (the 13 mirrored upper coefficients and 1 / u_pp), at
 //   ((k * NA + a) * plane + doff[d] + j - jmin(d)),  d = i + 2j,
 // in the logical coordinates of the solve (mirrored for the upper one).
+// One thread per packed position (k, q): the diagonal of q gives the point
+// (i, j, k) of the lower layout and, mirrored, the point (nx-1-i, ny-1-j,
+// nz-1-k) of the upper one; the thread reads each point's contiguous
+// coefficients and the lanes of a wavefront write consecutive doubles of
+// every array (a thread per point instead wrote every value into its own
+// write sector: 4x the stored bytes).
 __global__ void __launch_bounds__(256)
-    ilu0_pack_kernel(Grid g, const int *__restrict__ doff,
+    ilu0_pack_kernel(Grid g, const int *__restrict__ doff, int nd,
                      const double *__restrict__ L,
                      const double *__restrict__ U, double *__restrict__ Lp,
                      double *__restrict__ Up)
 {
     const int64_t n = g.size();
     const int64_t plane = (int64_t)g.nx * g.ny;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(p % g.nx);
-        const int64_t t = p / g.nx;
-        const int j = (int)(t % g.ny), k = (int)(t / g.ny);
-        {
-            const int d = i + 2 * j;
-            const int64_t o = doff[d] + j - ilb_jmin(d, g.nx);
+    for (int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; P < n;
+         P += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(P / plane);
+        const int q = (int)(P - k * plane);
+        int d, j;
+        ilb_locate(doff, nd, g.nx, q, d, j);
+        const int i = d - 2 * j;
+        const int64_t pl = ((int64_t)k * g.ny + j) * g.nx + i;
+        const int64_t pu = ((int64_t)(g.nz - 1 - k) * g.ny + (g.ny - 1 - j)) *
+                               g.nx +
+                           (g.nx - 1 - i);
+        double lv[13], uv[14];
 #pragma unroll
-            for (int a = 0; a < 13; ++a)
-                Lp[((int64_t)k * 13 + a) * plane + o] = L[13 * p + a];
-        }
-        {
-            const int iu = g.nx - 1 - i, ju = g.ny - 1 - j,
-                      ku = g.nz - 1 - k;
-            const int d = iu + 2 * ju;
-            const int64_t o = doff[d] + ju - ilb_jmin(d, g.nx);
-            // mirrored lower offset a' of the upper offset m = 26 - a'
+        for (int a = 0; a < 13; ++a) lv[a] = L[13 * pl + a];
 #pragma unroll
-            for (int a = 0; a < 13; ++a)
-                Up[((int64_t)ku * 14 + a) * plane + o] = U[14 * p + 13 - a];
-            Up[((int64_t)ku * 14 + 13) * plane + o] = 1.0 / U[14 * p];
-        }
+        for (int a = 0; a < 14; ++a) uv[a] = U[14 * pu + a];
+#pragma unroll
+        for (int a = 0; a < 13; ++a)
+            Lp[((int64_t)k * 13 + a) * plane + q] = lv[a];
+        // mirrored lower offset a' of the upper offset m = 26 - a'
+#pragma unroll
+        for (int a = 0; a < 13; ++a)
+            Up[((int64_t)k * 14 + a) * plane + q] = uv[13 - a];
+        Up[((int64_t)k * 14 + 13) * plane + q] = 1.0 / uv[0];
     }
 }
 
@@ -510,27 +535,37 @@ __global__ void __launch_bounds__(ILB_MAXT) ilu0_band_kernel(IlbArgs a)
     }
 }
 
-// r (natural) into the lower solve's packed order; z out of the upper
-// solve's (the lower order reversed: the mirrored diagonal i' + 2j' is
-// the reversed one, its rows in reverse order, the planes reversed).
+// r (natural) into the lower solve's packed order (a thread per packed
+// position, gathering, so that the stores are coalesced); z out of the
+// upper solve's (the lower order reversed: the mirrored diagonal i' + 2j' is
+// the reversed one, its rows in reverse order, the planes reversed; a thread
+// per natural point, gathering).
 __global__ void __launch_bounds__(256)
-    ilu0_pack_vec_kernel(Grid g, const int *__restrict__ doff,
+    ilu0_pack_vec_kernel(Grid g, const int *__restrict__ doff, int nd,
                          const double *__restrict__ v, double *__restrict__ vp,
                          int unpack_upper)
 {
     const int64_t n = g.size();
     const int64_t plane = (int64_t)g.nx * g.ny;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(p % g.nx);
-        const int64_t t = p / g.nx;
-        const int j = (int)(t % g.ny), k = (int)(t / g.ny);
-        const int d = i + 2 * j;
-        const int64_t pl = (int64_t)k * plane + doff[d] + j - ilb_jmin(d, g.nx);
-        if (unpack_upper)
-            vp[p] = v[n - 1 - pl];   // here v is the upper solve's output
-        else
-            vp[pl] = v[p];
+    for (int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; P < n;
+         P += (int64_t)gridDim.x * blockDim.x) {
+        if (unpack_upper) {
+            // P natural; its lower packed position pl, read reversed
+            const int i = (int)(P % g.nx);
+            const int64_t t = P / g.nx;
+            const int j = (int)(t % g.ny), k = (int)(t / g.ny);
+            const int d = i + 2 * j;
+            const int64_t pl =
+                (int64_t)k * plane + doff[d] + j - ilb_jmin(d, g.nx);
+            vp[P] = v[n - 1 - pl];
+        } else {
+            // P packed
+            const int k = (int)(P / plane);
+            const int q = (int)(P - k * plane);
+            int d, j;
+            ilb_locate(doff, nd, g.nx, q, d, j);
+            vp[P] = v[((int64_t)k * g.ny + j) * g.nx + (d - 2 * j)];
+        }
     }
 }
 
@@ -564,8 +599,9 @@ hipError_t launch_ilu0_pack(const m2s_stencil &A, const int *doff,
     const Grid g{A.ext.nx, A.ext.ny, A.ext.nz};
     const int64_t n = g.size();
     const int nb = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    const int nd = g.nx + 2 * g.ny - 1;
     hipLaunchKernelGGL(ilu0_pack_kernel, dim3(std::max(1, nb)), dim3(256), 0,
-                       s, g, doff, L, U, Lp, Up);
+                       s, g, doff, nd, L, U, Lp, Up);
     return hipGetLastError();
 }
 
@@ -617,8 +653,9 @@ hipError_t launch_ilu0_apply_packed(const m2s_stencil &A, const IlbLayout &L,
     a.spin_limit = e ? std::max(1, atoi(e)) : (1 << 22);
     // r into the lower solve's order (t), lower solve into y, upper solve
     // (reading y backwards) into t, t back into z's natural order
+    const int nd = g.nx + 2 * g.ny - 1;
     hipLaunchKernelGGL(ilu0_pack_vec_kernel, dim3(nb), dim3(256), 0, s, g,
-                       doff, r, t, 0);
+                       doff, nd, r, t, 0);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     for (int pass = 0; pass < 2; ++pass) {
@@ -640,7 +677,7 @@ hipError_t launch_ilu0_apply_packed(const m2s_stencil &A, const IlbLayout &L,
         if (err != hipSuccess) return err;
     }
     hipLaunchKernelGGL(ilu0_pack_vec_kernel, dim3(nb), dim3(256), 0, s, g,
-                       doff, t, z, 1);
+                       doff, nd, t, z, 1);
     return hipGetLastError();
 }
 
