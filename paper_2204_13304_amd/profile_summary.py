@@ -1,12 +1,17 @@
 """Summarise rocprofv3 CSV output per kernel and launch size.
 
     python -m paper_2204_13304_amd.profile_summary <rocprofv3 output dir>
+    python -m paper_2204_13304_amd.profile_summary <dir> --iteration KERNEL K
 
 Reads the rocpd SQLite database rocprofv3 writes by default (*.db), or
 its CSV output (--output-format csv), and prints: the per-kernel
 statistics (--stats); per (kernel name, grid size, workgroup size) the
 number of launches and the average / total duration (--kernel-trace);
 and per (kernel, grid size, counter) the mean value per dispatch (--pmc).
+With --iteration it lists instead, in launch order, the kernels of a trace
+database that ran after the (K-1)-th launch of a kernel whose name contains
+KERNEL, up to and including its K-th launch (one solver iteration when
+KERNEL is the iteration's last kernel), with their durations.
 Only the standard library is used.
 """
 from __future__ import annotations
@@ -120,7 +125,32 @@ def db_tables(path: str) -> str:
     return "\n".join(out)
 
 
+def iteration_table(path: str, kernel: str, k: int) -> str:
+    con = sqlite3.connect(path)
+    rows = con.execute("select name, grid_x, start, end, duration from "
+                       "kernels order by start").fetchall()
+    con.close()
+    ends = [i for i, r in enumerate(rows) if kernel in r[0]]
+    if k < 1 or k > len(ends):
+        return f"{len(ends)} launches of {kernel}: no iteration {k}"
+    a = ends[k - 2] + 1 if k > 1 else 0
+    b = ends[k - 1]
+    out = [f"### launches {a} .. {b} (iteration {k} of {len(ends)}): "
+           f"sum {sum(r[4] for r in rows[a:b + 1]) / 1e3:.1f} us, "
+           f"first start to last end {(rows[b][3] - rows[a][2]) / 1e3:.1f} us",
+           "kernel | grid | us"]
+    for name, gx, _, _, dur in rows[a:b + 1]:
+        out.append(f"{_short(name)} | {gx} | {dur / 1e3:.1f}")
+    return "\n".join(out)
+
+
 def main(argv):
+    if len(argv) == 5 and argv[2] == "--iteration":
+        for p in sorted(glob.glob(os.path.join(argv[1], "**", "*.db"),
+                                  recursive=True)):
+            print(f"## {os.path.relpath(p, argv[1])}")
+            print(iteration_table(p, argv[3], int(argv[4])))
+        return 0
     if len(argv) != 2:
         print(__doc__)
         return 2

@@ -188,3 +188,30 @@ def test_pcg_workspace_argument_errors():
                                 C.byref(opts), C.byref(info), None, None,
                                 None) == 1
     lib.m2s_pcg_workspace_destroy(None)   # a null workspace is ignored
+
+
+def test_profile_summary_lists_one_iteration(tmp_path):
+    # a synthetic trace database: two iterations of three kernels each
+    import sqlite3
+    from paper_2204_13304_amd import profile_summary as ps
+    db = tmp_path / "run_results.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, grid_x int, start int, "
+                "\"end\" int, duration int)")
+    t = 0
+    for it in range(2):
+        for name, dur in (("sweep", 500_000 + it), ("dot_kernel", 40_000),
+                          ("update_xr_kernel", 130_000)):
+            con.execute("insert into kernels values (?, ?, ?, ?, ?)",
+                        (name, 64, t, t + dur, dur))
+            t += dur
+    con.commit()
+    con.close()
+    out = ps.iteration_table(str(db), "update_xr_kernel", 2)
+    lines = out.splitlines()
+    assert "iteration 2 of 2" in lines[0] and "sum 670.0 us" in lines[0]
+    assert [ln.split(" | ")[0] for ln in lines[2:]] == [
+        "sweep", "dot_kernel", "update_xr_kernel"]
+    assert lines[2].endswith("| 500.0")
+    assert "no iteration 3" in ps.iteration_table(str(db),
+                                                  "update_xr_kernel", 3)
