@@ -13,7 +13,8 @@
 //
 // Each thread owns one column of the region and a contiguous range of its
 // rows; it walks down the rows keeping the three-value row sums of the
-// previous and current row in registers, so a point costs three LDS reads.
+// previous and current row in registers, so a point costs three LDS reads,
+// and takes the rows four at a time, their reads ahead of their stores.
 // The two iterate buffers and b fill a CU's LDS, so one workgroup per CU:
 // the launch is persistent (one workgroup per CU walking the tiles), and
 // the next tile's x and b region is loaded into registers while the
@@ -90,7 +91,8 @@ __global__ void __launch_bounds__(J9_NT)
             const double *src = (t & 1) ? xa : xb;
             double *dst = (t & 1) ? xb : xa;
             const int lo = t, hi = W - t;  // rows and columns computed
-            const int rows = (hi - lo + G - 1) / G;
+            // rows per group, a multiple of the 4-row groups below
+            const int rows = ((hi - lo + G - 1) / G + 3) & ~3;
             const int r0 = lo + grp * rows, r1 = min(hi, r0 + rows);
             if (grp < G && c >= lo && c < hi && r0 < r1) {
                 auto row3 = [&](int r, double &s3, double &side) {
@@ -102,15 +104,39 @@ __global__ void __launch_bounds__(J9_NT)
                 double sp, spd, sc, scd;
                 row3(r0 - 1, sp, spd);
                 row3(r0, sc, scd);
-#pragma unroll 4
-                for (int r = r0; r < r1; ++r) {
-                    double sn, snd;
-                    row3(r + 1, sn, snd);
+                // rows in groups of four: every LDS read of a group is
+                // issued before its first store (the compiler cannot tell
+                // the two iterate buffers apart, so it keeps a row's reads
+                // behind the previous row's store); b is read and the point
+                // computed whatever `in` says, then selected, since a
+                // branch around the read splits the rows into blocks too
+                auto point = [&](int r, double sn, double bv) {
                     const double sum = (sp + scd) + sn;
                     const int gy = gy0 + r;
                     const bool in = colin && gy >= 0 && gy < ny;
-                    dst[r * W + c] =
-                        in ? (bs[r * W + c] - off * sum) * inv_diag : 0.0;
+                    const double v = (bv - off * sum) * inv_diag;
+                    dst[r * W + c] = in ? v : 0.0;
+                };
+                int r = r0;
+                for (; r + 4 <= r1; r += 4) {
+                    double sn[4], snd[4], bv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        row3(r + 1 + u, sn[u], snd[u]);
+                        bv[u] = bs[(r + u) * W + c];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        point(r + u, sn[u], bv[u]);
+                        sp = sc;
+                        sc = sn[u];
+                        scd = snd[u];
+                    }
+                }
+                for (; r < r1; ++r) {
+                    double sn, snd;
+                    row3(r + 1, sn, snd);
+                    point(r, sn, bs[r * W + c]);
                     sp = sc;
                     sc = sn;
                     scd = snd;
