@@ -245,9 +245,11 @@ def test_ilu0_rejects_other_kinds_and_aliasing(m):
         m.ilu0_apply(A, Lg, Ug, r, r)
 
 
+# (6, 9, 1): one column, so every odd plane diagonal i + 2j is empty (the
+# packings' search for a position's diagonal skips them); (7, 1, 12): one row
 ILB_SHAPES = [(9, 13, 17), (20, 5, 33), (1, 1, 1), (3, 64, 10),
               (16, 16, 16), (5, 300, 7), (4, 512, 3), (11, 100, 9),
-              (2, 2, 130)]
+              (2, 2, 130), (6, 9, 1), (7, 1, 12)]
 
 
 @pytest.mark.parametrize("shape", ILB_SHAPES)
